@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of sgn(gamma5 Dw(mu)) x on one MI355X.
+
+Workload: 16^4 lattice, mu = 0.3 (two-sided Lanczos), m_w = -1, link width
+eps = 0.8 (gauge seed 0), one complex Gaussian source (seed 0), FP64.  One
+step is one whole application of the nested method (outer basis, nested
+small problem with Roberts-Higham, lift) at the (k, l) that reach relative
+accuracy 1e-8; the plain non-nested method is timed beside it at the same k.
+Accuracy of both is measured live against a non-nested reference run at
+k + 500.  Inputs are resident in device memory before timing starts.
+
+The JSON line also carries the roofline of the dominant kernel (the fused
+two-sided Lanczos stencil step), its average duration measured with HIP
+events on the launch stream over the timed steps, and the CPU oracle timed
+on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DIMS = (16, 16, 16, 16)
+MU = 0.3
+M_W = -1.0
+EPS = 0.8
+# algorithmic bytes per site of the fused two-sided Lanczos stencil step in
+# FP64: 4 links (576 B) + v_j, w_j, v_{j-1}, w_{j-1} read (4 x 192 B) + p, q
+# written (2 x 192 B)
+K1_BYTES_PER_SITE = 576 + 4 * 192 + 2 * 192
+HBM_PEAK_GBS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "k_bil1_16x16x16x16_pmc.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("krylov.hip", "stencil.h", "nk_internal.h"):
+        with open(os.path.join(ROOT, "paper_0910_2918_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def rel(a, b) -> float:
+    import torch
+
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def cpu_baseline(k: int, ell: int, sample_steps: int):
+    """The CPU oracle on a bounded sample of the workload, scaled to applies/s."""
+    import numpy as np
+
+    import latgen
+    from oracle import krylov as K
+    from oracle import nested as N
+    from oracle import wilson as W
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        blas_threads = 1
+    u = latgen.random_gauge(DIMS, EPS, 0)
+    x = latgen.random_sources(DIMS, 1, 0)[0]
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, MU).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -MU).reshape(-1)
+    t0 = time.perf_counter()
+    kr = K.two_sided_lanczos(f, fd, x.reshape(-1), sample_steps)
+    t_step = (time.perf_counter() - t0) / sample_steps
+    # lift: the same dense product over the sample's columns, scaled to k columns
+    z = np.ones(sample_steps, np.complex128)
+    t0 = time.perf_counter()
+    _ = kr.V @ z
+    t_lift = (time.perf_counter() - t0) * k / sample_steps
+    # small problem at full size on a Ritz matrix of the same order k (from a 4^4 run)
+    dims_s = (4, 4, 4, 4)
+    us = latgen.random_gauge(dims_s, EPS, 0)
+    xs = latgen.random_sources(dims_s, 1, 0)[0]
+    fs = lambda v: W.a_apply(us, v.reshape(xs.shape), M_W, MU).reshape(-1)
+    fds = lambda v: W.a_apply(us, v.reshape(xs.shape), M_W, -MU).reshape(-1)
+    H = K.two_sided_lanczos(fs, fds, xs.reshape(-1), k).H
+    t0 = time.perf_counter()
+    N.small_sign(H, ell, False)
+    t_small = time.perf_counter() - t0
+    t_apply = k * t_step + t_small + t_lift
+    return {
+        "value": 1.0 / t_apply,
+        "unit": "applies/s",
+        "cores": int(blas_threads),
+        "kind": "oracle",
+        "sample": (f"{sample_steps} two-sided Lanczos steps of the oracle at 16^4 (numpy, single-threaded stencil) "
+                   f"scaled to k={k}, plus the oracle's full nested small problem (k={k}, l={ell}; LAPACK with "
+                   f"{blas_threads} BLAS threads) and the lift product scaled from {sample_steps} columns"),
+        "t_step_s": t_step,
+        "t_small_s": t_small,
+        "t_lift_s": t_lift,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--k", type=int, default=450)
+    ap.add_argument("--ell", type=int, default=90)
+    ap.add_argument("--kref-extra", type=int, default=500)
+    ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--target", type=float, default=1e-8)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+
+    import latgen
+    from paper_0910_2918_amd import nk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    lib = nk.library()  # fails loudly if libnk.so is missing
+    del lib
+    dev = torch.device("cuda:0")
+    lat = nk.Lattice(DIMS)
+    nk.nk_gauge_set(lat.h, latgen.random_gauge(DIMS, EPS, 0))
+    x = torch.from_numpy(latgen.random_sources(DIMS, 1, 0)[0].reshape(-1)).to(dev)
+    y = torch.empty_like(x)
+    yref = torch.empty_like(x)
+
+    def params(k, ell, profile=0):
+        return nk.nk_sign_params_default(k=k, ell=ell, mu=MU, m_w=M_W, profile=profile)
+
+    # accuracy, untimed: reference = non-nested at k + kref_extra
+    kref = args.k + args.kref_extra
+    nk.nk_sign_apply_device(lat.h, params(kref, 0), x, yref)
+    nk.nk_sign_apply_device(lat.h, params(args.k, args.ell), x, y)
+    eps_nested = rel(y, yref)
+    nk.nk_sign_apply_device(lat.h, params(args.k, 0), x, y)
+    eps_plain = rel(y, yref)
+
+    # nested: warmup, then K timed steps (kernel durations recorded with HIP events)
+    for _ in range(args.warmup):
+        nk.nk_sign_apply_device(lat.h, params(args.k, args.ell), x, y)
+    torch.cuda.synchronize()
+    t_st = n_st = t_up = n_up = 0.0
+    ph = {"basis": 0.0, "small": 0.0, "lift": 0.0}
+    rh_iters = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info, rc = nk.nk_sign_apply_device(lat.h, params(args.k, args.ell, profile=1), x, y)
+        t_st += info.t_stencil_ms
+        n_st += info.n_stencil
+        t_up += info.t_update_ms
+        n_up += info.n_update
+        ph["basis"] += info.t_basis_ms
+        ph["small"] += info.t_small_ms
+        ph["lift"] += info.t_lift_ms
+        rh_iters = info.rh_iters
+    torch.cuda.synchronize()
+    t_nested = (time.perf_counter() - t0) / args.steps
+
+    # plain at the same k (fewer steps: it is timed for the comparison only)
+    nplain = max(1, args.steps // 2)
+    nk.nk_sign_apply_device(lat.h, params(args.k, 0), x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_small = 0.0
+    for _ in range(nplain):
+        info_p, _ = nk.nk_sign_apply_device(lat.h, params(args.k, 0), x, y)
+        plain_small += info_p.t_small_ms
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / nplain
+
+    V = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3]
+    k1_avg_s = (t_st / max(n_st, 1)) / 1e3
+    k1_bytes = K1_BYTES_PER_SITE * V
+    achieved = k1_bytes / k1_avg_s / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_PMC):
+        with open(PROFILE_PMC) as fh:
+            pmc = json.load(fh)
+        if pmc.get("source_hash") == kernel_source_hash():
+            traffic = pmc.get("bytes_per_launch")
+    out = {
+        "metric": "sgn(g5 Dw) x applies/sec at 16^4 mu=0.3, nested vs plain @1e-8; stencil HBM GB/s",
+        "value": 1.0 / t_nested,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_nested * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "16^4 lattice, mu=0.3 two-sided Lanczos, m_w=-1, random SU(3) links eps=0.8 seed 0, "
+                        "1 Gaussian source, nested sign at relative accuracy 1e-8",
+            "k": args.k,
+            "ell": args.ell,
+            "eps_nested": eps_nested,
+            "eps_plain": eps_plain,
+            "reference": f"non-nested k={kref}",
+        },
+        "plain": {"value": 1.0 / t_plain, "ms_per_step": t_plain * 1e3, "small_ms": plain_small / nplain},
+        "nested_vs_plain_speedup": t_plain / t_nested,
+        "phases_ms": {k: v / args.steps for k, v in ph.items()},
+        "rh_iters": rh_iters,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_bil1 (fused A v, A^dag w two-sided Lanczos stencil step, FP64)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "avg_launch_us": k1_avg_s * 1e6,
+            "launches": int(n_st),
+            "bytes_per_launch": k1_bytes,
+        },
+        "update_kernel": {"avg_launch_us": (t_up / max(n_up, 1)) * 1e3, "launches": int(n_up)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.k, args.ell, args.cpu_sample_steps)
+    lat.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,190 @@
+/*
+ * nk.h -- C ABI of the nested-Krylov sign-function library for MI355X (gfx950).
+ *
+ * The library computes y ~ sgn(A) x for A = gamma5 Dw(mu), the Wilson-Dirac
+ * operator with the Hasenfratz-Karsch chemical potential (Bloch & Heybrock,
+ * "A nested Krylov subspace method for the overlap operator", Sec. 1, Eq. (1)).
+ * The approximation is the Krylov/Ritz one of Sec. 2, Eq. (3): Lanczos at
+ * mu = 0 and two-sided Lanczos otherwise, and either the non-nested small
+ * problem sgn(H_k) e_1 by the Roberts-Higham iteration (Eq. (4)) or the nested
+ * one of Sec. 3, Eq. (5), with the preconditioning step H_k -> H_k + H_k^{-1}
+ * (Eq. (6)).
+ *
+ * Conventions (the paper leaves them open; these are fixed here):
+ *   dims = {Lx, Ly, Lz, Lt}, every L >= 2 and even; Lt is the temporal
+ *   direction (antiperiodic, carries mu); x, y, z are periodic.
+ *   A "canonical" spinor field is complex128, interleaved (re, im), indexed
+ *   [t][z][y][x][spin 4][colour 3]; n = 12 V complex entries, V = Lx Ly Lz Lt.
+ *   A canonical gauge field is complex128 [t][z][y][x][nu 4][3][3] with
+ *   U[..][nu][a][b] the SU(3) link from x to x + nu (nu = 0..3 = x, y, z, t).
+ *   gamma matrices: chiral Euclidean basis, gamma5 = diag(1, 1, -1, -1).
+ *   Dw(mu) psi(x) = (4 + m_w) psi(x) - 1/2 sum_nu [ e^{+mu d_{nu t}} (1 - gamma_nu)
+ *       U_nu(x) psi(x + nu) + e^{-mu d_{nu t}} (1 + gamma_nu) U_nu(x - nu)^dag psi(x - nu) ].
+ *
+ * Ownership: callers own every buffer they pass.  The library copies what it
+ * needs and keeps no user pointer after a call returns.  It owns its device
+ * workspaces (Krylov bases etc.), sized on first use and freed by
+ * nk_lattice_destroy.  A handle is not thread-safe: serialise calls on it.
+ *
+ * Errors: every entry point returns 0 (NK_OK) on success, a negative code on
+ * failure (outputs unspecified) or a positive warning (outputs valid).
+ * nk_last_error() returns a thread-local message for the last failure.
+ *
+ * "_device" variants take device pointers and a HIP stream (NULL = the
+ * default stream); they enqueue their work on that stream.  Host-pointer
+ * variants are synchronous.
+ */
+#ifndef NK_H
+#define NK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nk_lattice nk_lattice;
+typedef struct ihipStream_t* nk_stream_t; /* a hipStream_t */
+
+/* return codes */
+#define NK_OK 0
+#define NK_EINVAL (-1)      /* bad argument (dims, pointer, k, ell, nrhs, ...) */
+#define NK_ENOGAUGE (-2)    /* no gauge field set on the handle */
+#define NK_ENOMEM (-3)      /* device allocation failed (two_pass OFF and V_k does not fit) */
+#define NK_EHIP (-4)        /* a HIP runtime call failed */
+#define NK_WARN_NOTCONV 1   /* est > tol at k, or Roberts-Higham hit its iteration cap */
+#define NK_WARN_BREAKDOWN 2 /* two-sided Lanczos broke down; result uses the steps before it */
+
+/* precision of the outer Krylov recurrence (the small problem is always FP64) */
+#define NK_PREC_FP64 0
+#define NK_PREC_FP32 1           /* FP32 spinors and links, FP64 dots and coefficients */
+#define NK_PREC_FP32_BF16LINKS 2 /* as FP32 with links stored in BF16 (12 reals), SU(3) rebuilt in FP32 */
+
+/* Roberts-Higham scaling */
+#define NK_RH_NONE 0    /* the paper's unscaled iteration, Eq. (4) */
+#define NK_RH_DET 1     /* mu_n = |det S_n|^{-1/n} */
+#define NK_RH_LEARNED 2 /* per-step factors predicted by the small MLP, falling back to NK_RH_DET */
+
+/* two-pass lift */
+#define NK_TWO_PASS_AUTO 0 /* store V_k when it fits in device memory, else two passes */
+#define NK_TWO_PASS_ON 1   /* never store V_k: rebuild the basis in a second pass */
+#define NK_TWO_PASS_OFF 2  /* always store V_k (NK_ENOMEM if it does not fit) */
+
+typedef struct nk_sign_params {
+  double m_w;          /* Wilson mass, -2 < m_w < 0 (Sec. 1) */
+  double mu;           /* chemical potential; mu == 0 selects Hermitian Lanczos */
+  int32_t k;           /* outer Krylov size (maximum when tol > 0) */
+  int32_t ell;         /* inner Krylov size; 0 = non-nested method */
+  double tol;          /* stop early when est < tol (0 = always run k steps) */
+  int32_t nrhs;        /* number of sources (each its own Krylov space) */
+  int32_t precision;   /* NK_PREC_* */
+  int32_t rh_scaling;  /* NK_RH_* */
+  int32_t two_pass;    /* NK_TWO_PASS_* */
+  int32_t est_delay;   /* d of the estimate est = |z(k) - [z(k-d); 0]| / |z(k)|; 0 = no estimate */
+  int32_t check_every; /* steps between early-stop checks when tol > 0 */
+  int32_t rh_maxit;    /* Roberts-Higham iteration cap */
+  double rh_tol;       /* Roberts-Higham stop: |S_{n+1} - S_n|_F <= rh_tol |S_{n+1}|_F */
+  const int32_t* ell_per_rhs; /* optional host array [nrhs] of per-source ell (NULL = ell for all) */
+  int32_t profile;     /* 1: time every outer-recurrence kernel with HIP events on the caller's stream */
+  int32_t reserved;
+} nk_sign_params;
+
+typedef struct nk_sign_info {
+  int32_t k_used;         /* outer steps actually taken */
+  int32_t ell_used;       /* inner steps (0 for the non-nested method) */
+  int32_t rh_iters;       /* Roberts-Higham iterations on the small matrix */
+  int32_t breakdown_step; /* 2sL step of a serious breakdown, 0 = none */
+  int32_t two_pass;       /* 1 if the lift rebuilt the basis */
+  int32_t pad;
+  double est;             /* convergence estimate (NaN if not computed) */
+  double rh_residual;     /* |S (S e_1) - e_1| of the final Roberts-Higham iterate S (0 if sgn^2 = 1 holds on e_1) */
+  double t_basis_ms, t_small_ms, t_lift_ms;
+  /* with params.profile: summed durations and launch counts of the two
+   * outer-recurrence kernels (K1: stencil step, K2: update step) */
+  double t_stencil_ms, t_update_ms;
+  int32_t n_stencil, n_update;
+} nk_sign_info;
+
+/* Fill *p with defaults: m_w = -1, mu = 0, k = 100, ell = 0, tol = 0, nrhs = 1,
+ * FP64, unscaled RH, two_pass AUTO, est_delay = 0, check_every = 50,
+ * rh_maxit = 100, rh_tol = 1e-13, ell_per_rhs = NULL, profile = 0. */
+void nk_sign_params_default(nk_sign_params* p);
+
+/* Create a lattice context on the current HIP device.  dims = {Lx, Ly, Lz, Lt},
+ * each >= 2 and even.  NK_EINVAL on bad dims or out == NULL. */
+int nk_lattice_create(const int32_t dims[4], nk_lattice** out);
+
+/* Free the context and all its device memory.  NULL-safe. */
+int nk_lattice_destroy(nk_lattice* lat);
+
+/* Set the gauge field from a host array in canonical layout (4 V 9 complex128).
+ * Copied to the device in the library's own layout; the caller keeps U. */
+int nk_gauge_set(nk_lattice* lat, const double* U);
+
+/* As nk_gauge_set, from a device pointer (canonical layout), on `stream`. */
+int nk_gauge_set_device(nk_lattice* lat, const void* dU, nk_stream_t stream);
+
+/* y = Dw(mu) x (gamma5 == 0) or y = gamma5 Dw(mu) x (gamma5 != 0) for nrhs
+ * canonical vectors stored one after another (x, y: nrhs * 12 V complex128).
+ * The operator of Sec. 1; host pointers, synchronous.  x and y must not alias. */
+int nk_apply_dw(nk_lattice* lat, double m_w, double mu, int32_t gamma5,
+                const double* x, double* y, int32_t nrhs);
+
+/* Device-pointer variant of nk_apply_dw, asynchronous on `stream`. */
+int nk_apply_dw_device(nk_lattice* lat, double m_w, double mu, int32_t gamma5,
+                       const void* x, void* y, int32_t nrhs, nk_stream_t stream);
+
+/* The fused pair used by two-sided Lanczos (Sec. 2): av = A(mu) v and
+ * adw = A(mu)^dag w = A(-mu) w for A = gamma5 Dw, one link load for both.
+ * Canonical device vectors (12 V complex128 each); asynchronous on `stream`. */
+int nk_apply_pair_device(nk_lattice* lat, double m_w, double mu,
+                         const void* v, const void* w, void* av, void* adw,
+                         nk_stream_t stream);
+
+/* The outer Krylov basis only (Sec. 2): k steps of Lanczos (mu == 0) or
+ * two-sided Lanczos from x (canonical device vector), in p->precision.
+ * Writes the tridiagonal Ritz matrix H_k to host arrays: alpha[2k] (complex
+ * diagonal), beta[2k] (complex, beta[j] = H[j][j+1]), delta[2k] (complex,
+ * delta[j] = H[j+1][j]); entries past k_used are zero.  info may be NULL. */
+int nk_krylov_basis_device(nk_lattice* lat, const nk_sign_params* p, const void* x,
+                           double* alpha, double* beta, double* delta,
+                           nk_sign_info* info, nk_stream_t stream);
+
+/* The small problem on the device, from a host tridiagonal H_k (layout as
+ * above): z = sgn(H_k) e_1 (ell == 0, Eqs. (3)-(4)) or z = V_l sgn(H_l) e_1
+ * with the inner space K_l(H_k + H_k^{-1}, e_1) (Sec. 3, Eqs. (5)-(6)).
+ * hermitian != 0 selects inner Lanczos, else inner two-sided Lanczos.
+ * z: host complex128[k].  info may be NULL.  Synchronous. */
+int nk_small_sign(int32_t k, int32_t ell, int32_t hermitian,
+                  const double* alpha, const double* beta, const double* delta,
+                  const nk_sign_params* p, double* z, nk_sign_info* info);
+
+/* Roberts-Higham sign of `batch` dense complex matrices (Eq. (4)) on the
+ * device.  S: host complex128, matrix b at offset b * ld * ld, row-major,
+ * leading dimension ld, size n[b] <= ld.  On return S holds sgn(S) and
+ * iters[b] the iteration counts.  scaling = NK_RH_*.  Synchronous. */
+int nk_rh_sign(int32_t batch, int32_t ld, const int32_t* n, double* S,
+               int32_t scaling, int32_t maxit, double tol, int32_t* iters);
+
+/* y ~ sgn(gamma5 Dw(mu)) x (Eqs. (3)-(6)), nrhs canonical host vectors.
+ * Synchronous.  NK_WARN_* on a valid but unconverged/broken-down result.
+ * info may be NULL (for nrhs > 1 it describes the last source). */
+int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, double* y,
+                  nk_sign_info* info);
+
+/* Device-pointer variant; it synchronises `stream` before returning (the
+ * early-stop checks and the small problem need host decisions). */
+int nk_sign_apply_device(nk_lattice* lat, const nk_sign_params* p, const void* x, void* y,
+                         nk_sign_info* info, nk_stream_t stream);
+
+/* Thread-local message for the last failure ("" if none). */
+const char* nk_last_error(void);
+
+/* Library version string. */
+const char* nk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NK_H */

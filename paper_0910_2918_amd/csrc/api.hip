@@ -1,0 +1,581 @@
+// C ABI entry points (include/nk.h) and the host orchestration of one sign
+// application: outer basis -> small problem -> lift (Eqs. (3)-(6)).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "nk_internal.h"
+
+namespace nk {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  return NK_EHIP;
+}
+
+int DevBuf::ensure(size_t need) {
+  if (p && need <= bytes) return NK_OK;
+  release();
+  if (need == 0) return NK_OK;
+  hipError_t e = hipMalloc(&p, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    bytes = 0;
+    set_error("hipMalloc of %zu bytes failed: %s", need, hipGetErrorString(e));
+    return NK_ENOMEM;
+  }
+  bytes = need;
+  return NK_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+// per-call coefficient block on the device
+struct CoefBlock {
+  Coefs c;
+  C64* z;
+  C64* z0;
+  C64* xd;  // source in device layout (FP64)
+  C64* yd;  // result in device layout (FP64)
+};
+
+static int coef_block(nk_lattice* lat, int k, CoefBlock& cb) {
+  const size_t n = (size_t)12 * lat->g.V;
+  const size_t bytes = (size_t)(3 * k + 2 * (k + 1) + 2 * k) * sizeof(C64) + (size_t)(k + 1) * sizeof(double) +
+                       2 * n * sizeof(C64) + 64;
+  if (lat->coef.ensure(bytes)) return NK_ENOMEM;
+  char* p = lat->coef.as<char>();
+  auto take = [&](size_t b) {
+    char* r = p;
+    p += (b + 15) & ~(size_t)15;
+    return r;
+  };
+  cb.xd = (C64*)take(n * sizeof(C64));
+  cb.yd = (C64*)take(n * sizeof(C64));
+  cb.c.alpha = (C64*)take(k * sizeof(C64));
+  cb.c.beta = (C64*)take(k * sizeof(C64));
+  cb.c.delta = (C64*)take(k * sizeof(C64));
+  cb.c.sw = (C64*)take((k + 1) * sizeof(C64));
+  cb.z = (C64*)take(k * sizeof(C64));
+  cb.z0 = (C64*)take(k * sizeof(C64));
+  cb.c.sv = (double*)take((k + 1) * sizeof(double));
+  cb.c.flags = (int*)take(4 * sizeof(int));
+  return NK_OK;
+}
+
+static int validate_params(nk_lattice* lat, const nk_sign_params* p) {
+  if (!lat || !p) {
+    set_error("null handle or params");
+    return NK_EINVAL;
+  }
+  if (!lat->have_gauge) {
+    set_error("no gauge field set on the lattice handle");
+    return NK_ENOGAUGE;
+  }
+  if (p->k < 1 || p->ell < 0 || p->nrhs < 1 || p->precision < 0 || p->precision > 2 || p->rh_maxit < 1 ||
+      p->est_delay < 0 || p->est_delay >= p->k || !(p->tol >= 0.0) || p->two_pass < 0 || p->two_pass > 2 ||
+      p->rh_scaling < 0 || p->rh_scaling > 2 || !std::isfinite(p->mu) || !std::isfinite(p->m_w)) {
+    set_error("invalid sign parameters (k=%d ell=%d nrhs=%d precision=%d est_delay=%d)", p->k, p->ell, p->nrhs,
+              p->precision, p->est_delay);
+    return NK_EINVAL;
+  }
+  if (p->ell > p->k) {
+    set_error("ell (%d) > k (%d)", p->ell, p->k);
+    return NK_EINVAL;
+  }
+  if (p->tol > 0.0 && p->check_every < 1) {
+    set_error("check_every must be >= 1 when tol > 0");
+    return NK_EINVAL;
+  }
+  return NK_OK;
+}
+
+static double host_est(const std::vector<C64>& z1, const std::vector<C64>& z0) {
+  double num = 0, den = 0;
+  for (size_t i = 0; i < z1.size(); ++i) {
+    C64 d = z1[i];
+    if (i < z0.size()) d = d - z0[i];
+    num += norm2(d);
+    den += norm2(z1[i]);
+  }
+  return std::sqrt(num / den);
+}
+
+static int estimate(int kk, int ell, int herm, int d, const nk_sign_params* p, CoefBlock& cb, hipStream_t st,
+                    double* est) {
+  std::vector<C64> z1(kk), z0(kk - d);
+  SmallOut so;
+  int e = small_sign_dev(kk, ell, herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling, p->rh_maxit, p->rh_tol,
+                         cb.z0, &so, st, nullptr, 0);
+  if (e < 0) return e;
+  NK_HIP(hipMemcpyAsync(z1.data(), cb.z0, kk * sizeof(C64), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));
+  e = small_sign_dev(kk - d, std::min(ell, kk - d), herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling,
+                     p->rh_maxit, p->rh_tol, cb.z0, &so, st, nullptr, 0);
+  if (e < 0) return e;
+  NK_HIP(hipMemcpyAsync(z0.data(), cb.z0, (kk - d) * sizeof(C64), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));
+  *est = host_est(z1, z0);
+  return NK_OK;
+}
+
+// one source: x, y canonical device vectors
+static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64* x, C64* y, nk_sign_info* info,
+                    hipStream_t st) {
+  const Geom& g = lat->g;
+  const int k = p->k;
+  const int herm = p->mu == 0.0;
+  CoefBlock cb;
+  if (int e = coef_block(lat, k, cb)) return e;
+  BasisPlan bp;
+  bp.prec = p->precision;
+  bp.hermitian = herm;
+  bp.m_w = p->m_w;
+  bp.mu = p->mu;
+  bp.k = k;
+  // store V_k unless two passes are requested or it does not fit
+  const size_t vbytes = basis_vector_bytes(g, bp.prec) * (size_t)(k + 1);
+  int two = 0;
+  if (p->two_pass == NK_TWO_PASS_ON) {
+    two = 1;
+  } else {
+    size_t fr = 0, tot = 0;
+    NK_HIP(hipMemGetInfo(&fr, &tot));
+    const size_t avail = fr + lat->vk.bytes;
+    const size_t margin = (size_t)2 << 30;
+    if (vbytes + margin > avail) {
+      if (p->two_pass == NK_TWO_PASS_OFF) {
+        set_error("V_k needs %zu bytes; %zu available and two_pass is OFF", vbytes, avail);
+        return NK_ENOMEM;
+      }
+      two = 1;
+    }
+  }
+  bp.store = two ? 0 : 1;
+  bp.profile = p->profile ? 1 : 0;
+  lat->evkind.clear();
+  lat->evnext = 0;
+  if (!two && lat->vk.ensure(vbytes)) return NK_ENOMEM;
+  hipEvent_t ev[4];
+  for (auto& e : ev) NK_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+
+  if (int e = pack_spinor<double>(g, x, cb.xd, st)) return e;
+  NK_HIP(hipMemsetAsync(cb.c.flags, 0, 4 * sizeof(int), st));
+  NK_HIP(hipEventRecord(ev[0], st));
+  int kused = k;
+  double est = std::numeric_limits<double>::quiet_NaN();
+  int flag = 0;
+  const int stride = p->tol > 0.0 ? p->check_every : k;
+  for (int j0 = 0; j0 < k;) {
+    const int j1 = std::min(k, j0 + stride);
+    if (int e = basis_run(lat, bp, cb.xd, j0, j1, cb.c, lat->vk.p, st, nullptr)) return e;
+    j0 = j1;
+    if (p->tol > 0.0 && j1 < k) {
+      NK_HIP(hipMemcpyAsync(&flag, cb.c.flags, sizeof(int), hipMemcpyDeviceToHost, st));
+      NK_HIP(hipStreamSynchronize(st));
+      if (flag) break;
+      const int d = std::max(1, std::min(p->est_delay > 0 ? p->est_delay : 10, j1 - 1));
+      if (j1 - d < 1) continue;
+      double e1 = 0;
+      if (int e = estimate(j1, ell, herm, d, p, cb, st, &e1)) return e;
+      if (e1 < p->tol) {
+        kused = j1;
+        est = e1;
+        break;
+      }
+    }
+  }
+  NK_HIP(hipEventRecord(ev[1], st));
+  NK_HIP(hipMemcpyAsync(&flag, cb.c.flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));
+  int warn = NK_OK;
+  if (flag < 0) {
+    set_error("source vector has zero or non-finite norm");
+    return NK_EINVAL;
+  }
+  if (flag > 0) {
+    kused = std::min(kused, flag);
+    warn = NK_WARN_BREAKDOWN;
+    if (info) info->breakdown_step = flag;
+  }
+  SmallOut so;
+  int es = small_sign_dev(kused, std::min(ell, kused), herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling,
+                          p->rh_maxit, p->rh_tol, cb.z, &so, st, nullptr, 0);
+  if (es < 0) return es;
+  if (es > 0 && warn == NK_OK) warn = es;
+  if (p->est_delay > 0 && std::isnan(est) && kused - p->est_delay >= 1) {
+    if (int e = estimate(kused, ell, herm, p->est_delay, p, cb, st, &est)) return e;
+  }
+  NK_HIP(hipEventRecord(ev[2], st));
+  if (two) {
+    if (int e = two_pass_lift(lat, bp, cb.xd, kused, cb.z, cb.c, cb.yd, st)) return e;
+  } else {
+    if (int e = lift_run(lat, bp, kused, cb.z, 0.0, cb.c, lat->vk.p, cb.yd, st)) return e;
+  }
+  if (int e = unpack_spinor<double>(g, cb.yd, y, st)) return e;
+  NK_HIP(hipEventRecord(ev[3], st));
+  NK_HIP(hipEventSynchronize(ev[3]));
+  if (info) {
+    info->k_used = kused;
+    info->ell_used = so.ell_used;
+    info->rh_iters = so.rh_iters;
+    info->two_pass = two;
+    info->est = est;
+    info->rh_residual = so.rh_residual;
+    float t0 = 0, t1 = 0, t2 = 0;
+    (void)hipEventElapsedTime(&t0, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&t1, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&t2, ev[2], ev[3]);
+    info->t_basis_ms = t0;
+    info->t_small_ms = t1;
+    info->t_lift_ms = t2;
+  }
+  if (bp.profile) {
+    double a = 0, b = 0;
+    int na = 0, nb = 0;
+    if (int e = prof_collect(lat, &a, &b, &na, &nb)) return e;
+    if (info) {
+      info->t_stencil_ms += a;
+      info->t_update_ms += b;
+      info->n_stencil += na;
+      info->n_update += nb;
+    }
+  }
+  if (p->tol > 0.0 && !(est < p->tol) && warn == NK_OK) warn = NK_WARN_NOTCONV;
+  return warn;
+}
+
+}  // namespace nk
+
+nk_lattice::~nk_lattice() {
+  U64.release();
+  U32.release();
+  Ubf.release();
+  vk.release();
+  work.release();
+  coef.release();
+  part.release();
+  canon.release();
+  lift.release();
+  tmp.release();
+  for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+}
+
+using namespace nk;
+
+extern "C" {
+
+void nk_sign_params_default(nk_sign_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->m_w = -1.0;
+  p->mu = 0.0;
+  p->k = 100;
+  p->ell = 0;
+  p->tol = 0.0;
+  p->nrhs = 1;
+  p->precision = NK_PREC_FP64;
+  p->rh_scaling = NK_RH_NONE;
+  p->two_pass = NK_TWO_PASS_AUTO;
+  p->est_delay = 0;
+  p->check_every = 50;
+  p->rh_maxit = 100;
+  p->rh_tol = 1e-13;
+  p->ell_per_rhs = nullptr;
+}
+
+int nk_lattice_create(const int32_t dims[4], nk_lattice** out) {
+  if (!dims || !out) {
+    set_error("null argument");
+    return NK_EINVAL;
+  }
+  long long V = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 2 || (dims[i] & 1)) {
+      set_error("lattice extent %d in direction %d must be even and >= 2", dims[i], i);
+      return NK_EINVAL;
+    }
+    V *= dims[i];
+  }
+  if (12 * V >= (1LL << 31)) {
+    set_error("lattice too large (12 V must fit in 31 bits)");
+    return NK_EINVAL;
+  }
+  nk_lattice* lat = new nk_lattice();
+  lat->g.V = (int)V;
+  int st = 1;
+  for (int i = 0; i < 4; ++i) {
+    lat->g.L[i] = dims[i];
+    lat->g.stride[i] = st;
+    st *= dims[i];
+  }
+  if (hipGetDevice(&lat->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete lat;
+    set_error("no HIP device");
+    return NK_EHIP;
+  }
+  *out = lat;
+  return NK_OK;
+}
+
+int nk_lattice_destroy(nk_lattice* lat) {
+  if (!lat) return NK_OK;
+  (void)hipDeviceSynchronize();
+  delete lat;
+  return NK_OK;
+}
+
+int nk_gauge_set(nk_lattice* lat, const double* U) {
+  if (!lat || !U) {
+    set_error("null argument");
+    return NK_EINVAL;
+  }
+  const size_t bytes = (size_t)36 * lat->g.V * sizeof(C64);
+  if (lat->canon.ensure(bytes)) return NK_ENOMEM;
+  NK_HIP(hipMemcpy(lat->canon.p, U, bytes, hipMemcpyHostToDevice));
+  if (int e = pack_gauge(lat, lat->canon.as<C64>(), nullptr)) return e;
+  NK_HIP(hipDeviceSynchronize());
+  lat->have_gauge = true;
+  return NK_OK;
+}
+
+int nk_gauge_set_device(nk_lattice* lat, const void* dU, nk_stream_t stream) {
+  if (!lat || !dU) {
+    set_error("null argument");
+    return NK_EINVAL;
+  }
+  if (int e = pack_gauge(lat, (const C64*)dU, (hipStream_t)stream)) return e;
+  lat->have_gauge = true;
+  return NK_OK;
+}
+
+int nk_apply_dw_device(nk_lattice* lat, double m_w, double mu, int32_t gamma5, const void* x, void* y,
+                       int32_t nrhs, nk_stream_t stream) {
+  if (!lat || !x || !y || nrhs < 1 || x == y) {
+    set_error("invalid argument to nk_apply_dw");
+    return NK_EINVAL;
+  }
+  if (!lat->have_gauge) {
+    set_error("no gauge field set on the lattice handle");
+    return NK_ENOGAUGE;
+  }
+  const Geom& g = lat->g;
+  const size_t n = (size_t)12 * g.V;
+  if (lat->tmp.ensure(2 * n * sizeof(C64))) return NK_ENOMEM;
+  C64* a = lat->tmp.as<C64>();
+  C64* b = a + n;
+  hipStream_t st = (hipStream_t)stream;
+  for (int r = 0; r < nrhs; ++r) {
+    if (int e = pack_spinor<double>(g, (const C64*)x + r * n, a, st)) return e;
+    if (int e = apply_dw_dev(lat, m_w, mu, gamma5 ? 1 : 0, a, b, st)) return e;
+    if (int e = unpack_spinor<double>(g, b, (C64*)y + r * n, st)) return e;
+  }
+  return NK_OK;
+}
+
+int nk_apply_dw(nk_lattice* lat, double m_w, double mu, int32_t gamma5, const double* x, double* y, int32_t nrhs) {
+  if (!lat || !x || !y || nrhs < 1) {
+    set_error("invalid argument to nk_apply_dw");
+    return NK_EINVAL;
+  }
+  const size_t n = (size_t)12 * lat->g.V;
+  if (lat->canon.ensure(2 * n * nrhs * sizeof(C64))) return NK_ENOMEM;
+  C64* dx = lat->canon.as<C64>();
+  C64* dy = dx + n * nrhs;
+  NK_HIP(hipMemcpy(dx, x, n * nrhs * sizeof(C64), hipMemcpyHostToDevice));
+  if (int e = nk_apply_dw_device(lat, m_w, mu, gamma5, dx, dy, nrhs, nullptr)) return e;
+  NK_HIP(hipMemcpy(y, dy, n * nrhs * sizeof(C64), hipMemcpyDeviceToHost));
+  return NK_OK;
+}
+
+int nk_apply_pair_device(nk_lattice* lat, double m_w, double mu, const void* v, const void* w, void* av, void* adw,
+                         nk_stream_t stream) {
+  if (!lat || !v || !w || !av || !adw) {
+    set_error("invalid argument to nk_apply_pair_device");
+    return NK_EINVAL;
+  }
+  if (!lat->have_gauge) {
+    set_error("no gauge field set on the lattice handle");
+    return NK_ENOGAUGE;
+  }
+  const Geom& g = lat->g;
+  const size_t n = (size_t)12 * g.V;
+  if (lat->tmp.ensure(4 * n * sizeof(C64))) return NK_ENOMEM;
+  C64* t = lat->tmp.as<C64>();
+  hipStream_t st = (hipStream_t)stream;
+  if (int e = pack_spinor<double>(g, (const C64*)v, t, st)) return e;
+  if (int e = pack_spinor<double>(g, (const C64*)w, t + n, st)) return e;
+  if (int e = apply_pair_dev(lat, m_w, mu, t, t + n, t + 2 * n, t + 3 * n, st)) return e;
+  if (int e = unpack_spinor<double>(g, t + 2 * n, (C64*)av, st)) return e;
+  if (int e = unpack_spinor<double>(g, t + 3 * n, (C64*)adw, st)) return e;
+  return NK_OK;
+}
+
+int nk_krylov_basis_device(nk_lattice* lat, const nk_sign_params* p, const void* x, double* alpha, double* beta,
+                           double* delta, nk_sign_info* info, nk_stream_t stream) {
+  if (int e = validate_params(lat, p)) return e;
+  if (!x || !alpha || !beta || !delta) {
+    set_error("null argument");
+    return NK_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int k = p->k;
+  CoefBlock cb;
+  if (int e = coef_block(lat, k, cb)) return e;
+  BasisPlan bp{p->precision, p->mu == 0.0 ? 1 : 0, p->m_w, p->mu, k, 0, 0};
+  if (int e = pack_spinor<double>(lat->g, (const C64*)x, cb.xd, st)) return e;
+  NK_HIP(hipMemsetAsync(cb.c.flags, 0, 4 * sizeof(int), st));
+  NK_HIP(hipMemsetAsync(cb.c.alpha, 0, 3 * k * sizeof(C64), st));
+  if (int e = basis_run(lat, bp, cb.xd, 0, k, cb.c, nullptr, st, nullptr)) return e;
+  int flag = 0;
+  NK_HIP(hipMemcpyAsync(&flag, cb.c.flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipMemcpyAsync(alpha, cb.c.alpha, k * sizeof(C64), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipMemcpyAsync(beta, cb.c.beta, k * sizeof(C64), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipMemcpyAsync(delta, cb.c.delta, k * sizeof(C64), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));
+  if (flag < 0) {
+    set_error("source vector has zero or non-finite norm");
+    return NK_EINVAL;
+  }
+  const int kused = flag > 0 ? flag : k;
+  // entries past k_used (and the last off-diagonal) are zero
+  for (int j = kused; j < k; ++j) alpha[2 * j] = alpha[2 * j + 1] = 0.0;
+  for (int j = kused - 1; j < k; ++j) beta[2 * j] = beta[2 * j + 1] = delta[2 * j] = delta[2 * j + 1] = 0.0;
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->k_used = kused;
+    info->breakdown_step = flag;
+    info->est = std::numeric_limits<double>::quiet_NaN();
+  }
+  return flag > 0 ? NK_WARN_BREAKDOWN : NK_OK;
+}
+
+int nk_small_sign(int32_t k, int32_t ell, int32_t hermitian, const double* alpha, const double* beta,
+                  const double* delta, const nk_sign_params* p, double* z, nk_sign_info* info) {
+  if (k < 1 || ell < 0 || ell > k || !alpha || !beta || !delta || !z) {
+    set_error("invalid argument to nk_small_sign");
+    return NK_EINVAL;
+  }
+  nk_sign_params dp;
+  nk_sign_params_default(&dp);
+  if (!p) p = &dp;
+  DevBuf buf;
+  if (buf.ensure((size_t)4 * k * sizeof(C64))) return NK_ENOMEM;
+  C64* a = buf.as<C64>();
+  NK_HIP(hipMemcpy(a, alpha, k * sizeof(C64), hipMemcpyHostToDevice));
+  NK_HIP(hipMemcpy(a + k, beta, k * sizeof(C64), hipMemcpyHostToDevice));
+  NK_HIP(hipMemcpy(a + 2 * k, delta, k * sizeof(C64), hipMemcpyHostToDevice));
+  SmallOut so;
+  int e = small_sign_dev(k, ell, hermitian, a, a + k, a + 2 * k, p->rh_scaling, p->rh_maxit, p->rh_tol, a + 3 * k,
+                         &so, nullptr, nullptr, 0);
+  if (e < 0) return e;
+  NK_HIP(hipMemcpy(z, a + 3 * k, k * sizeof(C64), hipMemcpyDeviceToHost));
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->k_used = k;
+    info->ell_used = so.ell_used;
+    info->rh_iters = so.rh_iters;
+    info->rh_residual = so.rh_residual;
+    info->est = std::numeric_limits<double>::quiet_NaN();
+  }
+  return e;
+}
+
+int nk_rh_sign(int32_t batch, int32_t ld, const int32_t* n, double* S, int32_t scaling, int32_t maxit, double tol,
+               int32_t* iters) {
+  if (batch < 1 || ld < 1 || !n || !S || !iters || maxit < 1 || scaling < 0 || scaling > 1) {
+    set_error("invalid argument to nk_rh_sign");
+    return NK_EINVAL;
+  }
+  for (int b = 0; b < batch; ++b)
+    if (n[b] < 0 || n[b] > ld) {
+      set_error("matrix %d has size %d outside [0, ld=%d]", b, n[b], ld);
+      return NK_EINVAL;
+    }
+  DevBuf buf;
+  const size_t bytes = (size_t)batch * ld * ld * sizeof(C64);
+  if (buf.ensure(bytes)) return NK_ENOMEM;
+  NK_HIP(hipMemcpy(buf.p, S, bytes, hipMemcpyHostToDevice));
+  int e = rh_sign_batched(batch, ld, n, buf.as<C64>(), scaling, maxit, tol, iters, nullptr, nullptr, nullptr, 0);
+  if (e < 0) return e;
+  NK_HIP(hipMemcpy(S, buf.p, bytes, hipMemcpyDeviceToHost));
+  return e;
+}
+
+int nk_sign_apply_device(nk_lattice* lat, const nk_sign_params* p, const void* x, void* y, nk_sign_info* info,
+                         nk_stream_t stream) {
+  if (int e = validate_params(lat, p)) return e;
+  if (!x || !y || x == y) {
+    set_error("invalid source/result pointers");
+    return NK_EINVAL;
+  }
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->est = std::numeric_limits<double>::quiet_NaN();
+  }
+  const size_t n = (size_t)12 * lat->g.V;
+  int worst = NK_OK;
+  for (int r = 0; r < p->nrhs; ++r) {
+    const int ell = p->ell_per_rhs ? p->ell_per_rhs[r] : p->ell;
+    if (ell < 0 || ell > p->k) {
+      set_error("ell_per_rhs[%d] = %d outside [0, k]", r, ell);
+      return NK_EINVAL;
+    }
+    int e = sign_one(lat, p, ell, (const C64*)x + r * n, (C64*)y + r * n, info, (hipStream_t)stream);
+    if (e < 0) return e;
+    if (e > worst) worst = e;
+  }
+  return worst;
+}
+
+int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, double* y, nk_sign_info* info) {
+  if (int e = validate_params(lat, p)) return e;
+  if (!x || !y) {
+    set_error("null argument");
+    return NK_EINVAL;
+  }
+  const size_t n = (size_t)12 * lat->g.V * p->nrhs;
+  DevBuf io;
+  if (io.ensure(2 * n * sizeof(C64))) return NK_ENOMEM;
+  C64* dx = io.as<C64>();
+  C64* dy = dx + n;
+  NK_HIP(hipMemcpy(dx, x, n * sizeof(C64), hipMemcpyHostToDevice));
+  int e = nk_sign_apply_device(lat, p, dx, dy, info, nullptr);
+  if (e < 0) return e;
+  NK_HIP(hipMemcpy(y, dy, n * sizeof(C64), hipMemcpyDeviceToHost));
+  return e;
+}
+
+const char* nk_last_error(void) { return g_err.c_str(); }
+
+const char* nk_version(void) { return "nk 0.1.0 (gfx950)"; }
+
+}  // extern "C"

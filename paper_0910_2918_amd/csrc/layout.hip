@@ -1,0 +1,74 @@
+// Canonical (site-major) <-> device (component-major) layouts.
+#include "nk_internal.h"
+
+namespace nk {
+
+__device__ __forceinline__ uint32_t f2bf16(float f) {
+  // round to nearest even
+  uint32_t b = __float_as_uint(f);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return b >> 16;
+}
+
+// canonical U[site][nu][a][b] -> U64/U32 [(nu*9 + a*3 + b) * V + site], Ubf [(nu*6 + e) * V + site]
+__global__ void k_pack_gauge(int V, const C64* __restrict__ canon, C64* __restrict__ u64, C32* __restrict__ u32,
+                             uint32_t* __restrict__ ubf) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+  for (int nu = 0; nu < 4; ++nu) {
+    for (int e = 0; e < 9; ++e) {
+      C64 v = canon[(size_t)s * 36 + nu * 9 + e];
+      u64[(size_t)(nu * 9 + e) * V + s] = v;
+      u32[(size_t)(nu * 9 + e) * V + s] = narrow<float>(v);
+      if (e < 6) ubf[(size_t)(nu * 6 + e) * V + s] = f2bf16((float)v.re) | (f2bf16((float)v.im) << 16);
+    }
+  }
+}
+
+template <class R>
+__global__ void k_pack_spinor(int V, const C64* __restrict__ canon, Cx<R>* __restrict__ dev) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) dev[(size_t)c * V + s] = narrow<R>(canon[(size_t)s * 12 + c]);
+}
+
+template <class R>
+__global__ void k_unpack_spinor(int V, const Cx<R>* __restrict__ dev, C64* __restrict__ canon) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= V) return;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) canon[(size_t)s * 12 + c] = widen(dev[(size_t)c * V + s]);
+}
+
+int pack_gauge(nk_lattice* lat, const C64* canon, hipStream_t st) {
+  const int V = lat->g.V;
+  if (lat->U64.ensure((size_t)36 * V * sizeof(C64)) || lat->U32.ensure((size_t)36 * V * sizeof(C32)) ||
+      lat->Ubf.ensure((size_t)24 * V * sizeof(uint32_t)))
+    return NK_ENOMEM;
+  hipLaunchKernelGGL(k_pack_gauge, dim3((V + 255) / 256), dim3(256), 0, st, V, canon, lat->U64.as<C64>(),
+                     lat->U32.as<C32>(), lat->Ubf.as<uint32_t>());
+  NK_HIP(hipGetLastError());
+  return NK_OK;
+}
+
+template <class R>
+int pack_spinor(const Geom& g, const C64* canon, Cx<R>* dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_spinor<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g.V, canon, dev);
+  NK_HIP(hipGetLastError());
+  return NK_OK;
+}
+
+template <class R>
+int unpack_spinor(const Geom& g, const Cx<R>* dev, C64* canon, hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack_spinor<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g.V, dev, canon);
+  NK_HIP(hipGetLastError());
+  return NK_OK;
+}
+
+template int pack_spinor<double>(const Geom&, const C64*, C64*, hipStream_t);
+template int pack_spinor<float>(const Geom&, const C64*, C32*, hipStream_t);
+template int unpack_spinor<double>(const Geom&, const C64*, C64*, hipStream_t);
+template int unpack_spinor<float>(const Geom&, const C32*, C64*, hipStream_t);
+
+}  // namespace nk

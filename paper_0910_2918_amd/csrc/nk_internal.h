@@ -1,0 +1,175 @@
+// Internal declarations of the nested-Krylov sign-function library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nk.h"
+
+namespace nk {
+
+// ---------------------------------------------------------------------------
+// complex numbers in registers and memory (8- or 16-byte aligned pairs)
+template <class R>
+struct __align__(2 * sizeof(R)) Cx {
+  R re, im;
+};
+
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> mk(R a, R b) {
+  Cx<R> z;
+  z.re = a;
+  z.im = b;
+  return z;
+}
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return mk(a.re + b.re, a.im + b.im); }
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return mk(a.re - b.re, a.im - b.im); }
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return mk(s * a.re, s * a.im); }
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// conj(a) * b
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> cmulc(Cx<R> a, Cx<R> b) {
+  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> conj(Cx<R> a) { return mk(a.re, -a.im); }
+template <class R>
+__host__ __device__ __forceinline__ R norm2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+using C64 = Cx<double>;
+using C32 = Cx<float>;
+
+template <class R>
+__host__ __device__ __forceinline__ Cx<double> widen(Cx<R> a) { return mk<double>((double)a.re, (double)a.im); }
+template <class R>
+__host__ __device__ __forceinline__ Cx<R> narrow(Cx<double> a) { return mk<R>((R)a.re, (R)a.im); }
+
+// ---------------------------------------------------------------------------
+// lattice geometry: dims {Lx, Ly, Lz, Lt}, site = ((t Lz + z) Ly + y) Lx + x
+struct Geom {
+  int L[4];
+  int stride[4];  // 1, Lx, Lx Ly, Lx Ly Lz
+  int V;
+};
+
+// device spinor layout: component c = spin*3 + colour is a contiguous array
+// of V complex numbers: field[c * V + site].  Krylov vectors live in this
+// layout; only pack/unpack see the canonical site-major order.
+// device link layout: U[(nu * 9 + a * 3 + b) * V + site] (FP64 / FP32), or
+// for BF16 storage Ub[(nu * 12 + r) * V + site], r = the 12 reals of rows 0, 1.
+
+// ---------------------------------------------------------------------------
+// error state
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define NK_HIP(call)                                                  \
+  do {                                                                \
+    hipError_t _e = (call);                                           \
+    if (_e != hipSuccess) return ::nk::hip_fail(_e, #call, __FILE__, __LINE__); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// simple growable device buffer
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need);
+  void release();
+  template <class T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+}  // namespace nk
+
+// the opaque handle
+struct nk_lattice {
+  nk::Geom g;
+  int device = 0;
+  bool have_gauge = false;
+  nk::DevBuf U64, U32, Ubf;  // gauge field in the three storage formats
+  // workspaces of the outer recurrence
+  nk::DevBuf vk;       // outer basis V_k (unnormalised columns)
+  nk::DevBuf work;     // p, q, W ring, scratch vectors
+  nk::DevBuf coef;     // alpha, beta, delta, scales, flags
+  nk::DevBuf part;     // per-workgroup partial sums
+  nk::DevBuf canon;    // canonical-layout staging for host calls
+  nk::DevBuf lift;     // lift coefficients
+  nk::DevBuf tmp;      // device-layout temporaries of the stand-alone operator calls
+  // optional per-launch timing of the outer-recurrence kernels
+  std::vector<hipEvent_t> evpool;
+  std::vector<int> evkind;  // kind of each recorded (start, stop) pair: 0 = K1, 1 = K2
+  size_t evnext = 0;
+  ~nk_lattice();
+};
+
+namespace nk {
+
+// ----- launchers implemented in the .hip files ------------------------------
+// layout.hip
+int pack_gauge(nk_lattice* lat, const C64* canon, hipStream_t st);
+template <class R>
+int pack_spinor(const Geom& g, const C64* canon, Cx<R>* dev, hipStream_t st);
+template <class R>
+int unpack_spinor(const Geom& g, const Cx<R>* dev, C64* canon, hipStream_t st);
+
+// wilson.hip
+int apply_dw_dev(nk_lattice* lat, double m_w, double mu, int g5, const C64* x, C64* y, hipStream_t st);
+int apply_pair_dev(nk_lattice* lat, double m_w, double mu, const C64* v, const C64* w, C64* av, C64* adw,
+                   hipStream_t st);
+int apply_g5dw_any(nk_lattice* lat, int prec, double m_w, double mu, const void* x, void* y, hipStream_t st);
+
+// krylov.hip -- outer basis; coefficient arrays stay on the device
+struct Coefs {
+  C64* alpha;  // [k]
+  C64* beta;   // [k]  beta[j]  = H[j][j+1]
+  C64* delta;  // [k]  delta[j] = H[j+1][j]
+  double* sv;  // [k+1] v_j = sv[j] * vt_j
+  C64* sw;     // [k+1] w_j = sw[j] * wt_j
+  int* flags;  // [4]: 0 = breakdown step (0 = none)
+};
+struct BasisPlan {
+  int prec;       // NK_PREC_*
+  int hermitian;  // Lanczos (1) or 2sL (0)
+  double m_w, mu;
+  int k;
+  int store;      // 1: keep every column in V_k; 0: ring of 3 columns (two-pass sweeps)
+  int profile;    // bracket every K1 / K2 launch with HIP events
+};
+size_t basis_vector_bytes(const Geom& g, int prec);
+int basis_run(nk_lattice* lat, const BasisPlan& bp, const C64* x_canon, int j0, int j1, Coefs c, void* vk,
+              hipStream_t st, int* breakdown_out);
+// sum the recorded kernel durations (after a synchronisation) and reset the record
+int prof_collect(nk_lattice* lat, double* t_k1, double* t_k2, int* n_k1, int* n_k2);
+int lift_run(nk_lattice* lat, const BasisPlan& bp, int kused, const C64* z, double xnorm_dummy, Coefs c,
+             const void* vk, C64* y_canon, hipStream_t st);
+int two_pass_lift(nk_lattice* lat, const BasisPlan& bp, const C64* x_canon, int kused, const C64* z, Coefs c,
+                  C64* y_canon, hipStream_t st);
+
+// small.hip -- the small problem on the device
+struct SmallOut {
+  int rh_iters = 0;
+  int ell_used = 0;
+  double rh_residual = 0;
+};
+// mu_sched: optional host array [mu_steps] of Roberts-Higham scale factors (NK_RH_LEARNED)
+int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,
+                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st,
+                   const double* mu_sched, int mu_steps);
+
+// rh.hip -- batched Roberts-Higham on dense matrices (S on the device, row-major,
+// matrix b at b * ld * ld); mu_sched: host [batch][mu_steps] factors for NK_RH_LEARNED
+int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
+                    int* iters_host, double* resid_host, hipStream_t st, const double* mu_sched, int mu_steps);
+
+}  // namespace nk

@@ -1,0 +1,440 @@
+// Roberts-Higham iteration S_{n+1} = (S_n + S_n^{-1}) / 2 (Eq. (4)) for a
+// batch of dense complex matrices of uneven sizes, on gfx950.
+//
+// The inverse is an out-of-place blocked Gauss-Jordan elimination with
+// partial pivoting.  For each panel of NB columns:
+//  * k_gj_panel (one 1024-thread workgroup per matrix) eliminates the panel
+//    columns in registers: pivot search over the rows not yet used, row
+//    bookkeeping in LDS (the rows themselves are not moved), and writes the
+//    transformed panel M in pivot order plus the panel's row permutation;
+//  * k_gj_update applies the rank-NB update to every other column,
+//      new[pos][j] = (pos in panel ? 0 : old[src(pos)][j]) + sum_t M[pos][t] old[src(c0 + t)][j],
+//    reading the previous buffer and writing the other one (ping-pong), so
+//    no workgroup ever reads a row another one is writing.
+// k_rh_combine undoes the accumulated row permutation as a column
+// permutation of the inverse, forms the average (optionally with a positive
+// scale mu, which leaves the limit unchanged) and emits partial sums of
+// |S_{n+1} - S_n|_F^2 and |S_{n+1}|_F^2 for the host's stopping test.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "nk_internal.h"
+
+namespace nk {
+
+constexpr int PT = 1024;  // panel threads
+constexpr int UT = 256;   // update threads, 64 x 64 tile
+
+__device__ __forceinline__ double cabs1(C64 a) { return fabs(a.re) + fabs(a.im); }
+
+__device__ __forceinline__ C64 cinv(C64 a) {
+  // 1 / a, scaled to avoid overflow in |a|^2
+  const double s = fmax(fabs(a.re), fabs(a.im));
+  const double ar = a.re / s, ai = a.im / s;
+  const double d = (ar * ar + ai * ai) * s;
+  return mk(ar / d, -ai / d);
+}
+
+template <int NB, int RM>
+__global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
+                                                 int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
+                                                 int* __restrict__ p2r_b, int* __restrict__ perm_b,
+                                                 double* __restrict__ logdet, int* __restrict__ sing) {
+  const int b = blockIdx.x;
+  const int n = nvec[b];
+  if (!active[b] || c0 >= n) return;
+  const int nbe = min(NB, n - c0);
+  const size_t off = (size_t)b * ld * ld;
+  const C64* Aold = Aold_b + off;
+  C64* Anew = Anew_b + off;
+  int* p2r = p2r_b + (size_t)b * ld;
+  int* perm = perm_b + (size_t)b * ld;
+
+  __shared__ int s_p2r[PT * RM];
+  __shared__ int s_r2p[PT * RM];
+  __shared__ C64 s_prow[NB];
+  __shared__ double s_val[PT / 64];
+  __shared__ int s_pos[PT / 64];
+  __shared__ double s_ld;
+  __shared__ int s_sing;
+
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  C64 a[RM][NB];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int r = tid + m * PT;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) a[m][t] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
+  }
+  for (int r = tid; r < n; r += PT) {
+    s_p2r[r] = r;
+    s_r2p[r] = r;
+  }
+  if (tid == 0) {
+    s_ld = 0.0;
+    s_sing = 0;
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    if (t < nbe) {
+      const int c = c0 + t;
+      double best = -1.0;
+      int bpos = 0x7fffffff;
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const int r = tid + m * PT;
+        if (r < n) {
+          const int pos = s_r2p[r];
+          const double v = cabs1(a[m][t]);
+          if (pos >= c && (v > best || (v == best && pos < bpos))) {
+            best = v;
+            bpos = pos;
+          }
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int op = __shfl_xor(bpos, o, 64);
+        if (ov > best || (ov == best && op < bpos)) {
+          best = ov;
+          bpos = op;
+        }
+      }
+      if (lane == 0) {
+        s_val[wid] = best;
+        s_pos[wid] = bpos;
+      }
+      __syncthreads();
+      best = s_val[0];
+      bpos = s_pos[0];
+#pragma unroll
+      for (int w = 1; w < PT / 64; ++w) {
+        const double ov = s_val[w];
+        const int op = s_pos[w];
+        if (ov > best || (ov == best && op < bpos)) {
+          best = ov;
+          bpos = op;
+        }
+      }
+      const int p = bpos;
+      const int pr = s_p2r[p];
+      const int rc = s_p2r[c];
+      if ((pr & (PT - 1)) == tid) {
+#pragma unroll
+        for (int m = 0; m < RM; ++m) {
+          if (m == pr / PT) {
+            const C64 piv = a[m][t];
+            if (!(best > 0.0)) s_sing = 1;
+            const C64 d = cinv(piv);
+            s_ld += log(sqrt(piv.re * piv.re + piv.im * piv.im));
+#pragma unroll
+            for (int u = 0; u < NB; ++u) s_prow[u] = (u == t) ? d : cmul(a[m][u], d);
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        s_p2r[c] = pr;
+        s_p2r[p] = rc;
+        s_r2p[pr] = c;
+        s_r2p[rc] = p;
+      }
+#pragma unroll
+      for (int m = 0; m < RM; ++m) {
+        const int r = tid + m * PT;
+        if (r < n) {
+          if (r == pr) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) a[m][u] = s_prow[u];
+          } else {
+            const C64 f = a[m][t];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+              const C64 base = (u == t) ? mk(0.0, 0.0) : a[m][u];
+              a[m][u] = base - cmul(f, s_prow[u]);
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // M in pivot order, the panel's position -> source-row map, the running permutation
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int r = tid + m * PT;
+    if (r < n) {
+      const int pos = s_r2p[r];
+#pragma unroll
+      for (int t = 0; t < NB; ++t)
+        if (t < nbe) Anew[(size_t)pos * ld + c0 + t] = a[m][t];
+    }
+  }
+  int pv[RM];
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int pos = tid + m * PT;
+    pv[m] = pos < n ? perm[s_p2r[pos]] : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < RM; ++m) {
+    const int pos = tid + m * PT;
+    if (pos < n) {
+      perm[pos] = pv[m];
+      p2r[pos] = s_p2r[pos];
+    }
+  }
+  if (tid == 0) {
+    logdet[b] += s_ld;
+    if (s_sing) sing[b] = 1;
+  }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(UT) k_gj_update(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
+                                                  int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
+                                                  const int* __restrict__ p2r_b) {
+  const int b = blockIdx.z;
+  const int n = nvec[b];
+  if (!active[b] || c0 >= n) return;
+  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+  if (row0 >= n || col0 >= n) return;
+  const int nbe = min(NB, n - c0);
+  const size_t off = (size_t)b * ld * ld;
+  const C64* Aold = Aold_b + off;
+  C64* Anew = Anew_b + off;
+  const int* p2r = p2r_b + (size_t)b * ld;
+  __shared__ C64 sM[64][NB + 1];
+  __shared__ C64 sR[NB][64 + 1];
+  __shared__ int sP[64];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * NB; e += UT) {
+    const int i = e / NB, t = e % NB;
+    const int pos = row0 + i;
+    sM[i][t] = (pos < n && t < nbe) ? Anew[(size_t)pos * ld + c0 + t] : mk(0.0, 0.0);
+  }
+  for (int e = tid; e < 64 * NB; e += UT) {
+    const int t = e / 64, j = e % 64;
+    const int col = col0 + j;
+    sR[t][j] = (t < nbe && col < n) ? Aold[(size_t)p2r[c0 + t] * ld + col] : mk(0.0, 0.0);
+  }
+  if (tid < 64) sP[tid] = (row0 + tid < n) ? p2r[row0 + tid] : 0;
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const int i = ty * 4 + ii;
+    const int pos = row0 + i;
+    if (pos >= n) continue;
+    const bool inpanel = pos >= c0 && pos < c0 + nbe;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = tx + 16 * q;
+      const int col = col0 + j;
+      if (col >= n || (col >= c0 && col < c0 + nbe)) continue;
+      C64 acc = inpanel ? mk(0.0, 0.0) : Aold[(size_t)sP[i] * ld + col];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) acc = acc + cmul(sM[i][t], sR[t][j]);
+      Anew[(size_t)pos * ld + col] = acc;
+    }
+  }
+}
+
+__global__ void k_rh_start(int ld, int batch, const int* __restrict__ nvec, const int* __restrict__ active,
+                           int* __restrict__ perm_b, double* __restrict__ logdet) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const int n = nvec[b];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    perm_b[(size_t)b * ld + i] = i;
+  if (blockIdx.x == 0 && threadIdx.x == 0) logdet[b] = 0.0;
+}
+
+// G0/G1: the ping-pong buffers; a matrix of order n ends its elimination in
+// the buffer of its own last panel, (ceil(n / nb) - 1) % 2.
+__global__ void __launch_bounds__(256) k_rh_combine(int ld, int nb, const int* __restrict__ nvec,
+                                                    const int* __restrict__ active, const C64* __restrict__ G0,
+                                                    const C64* __restrict__ G1,
+                                                    C64* __restrict__ X_b, const int* __restrict__ perm_b,
+                                                    const double* __restrict__ logdet, int scaling,
+                                                    const double* __restrict__ mu_in, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  const int n = nvec[b];
+  double dsum = 0.0, nsum = 0.0;
+  if (active[b]) {
+    double mu = 1.0;
+    if (scaling == NK_RH_DET) mu = exp(-logdet[b] / n);
+    else if (scaling == NK_RH_LEARNED && mu_in && mu_in[b] > 0.0) mu = mu_in[b];
+    const double imu = 1.0 / mu;
+    const size_t off = (size_t)b * ld * ld;
+    const int npan = (n + nb - 1) / nb;
+    const C64* G = (((npan - 1) & 1) ? G1 : G0) + off;
+    C64* X = X_b + off;
+    const int* perm = perm_b + (size_t)b * ld;
+    const size_t nn = (size_t)n * n;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nn; e += (size_t)gridDim.x * 256) {
+      const int i = (int)(e / n), p = (int)(e % n);
+      const size_t xi = (size_t)i * ld + perm[p];
+      const C64 xs = mu * X[xi];
+      const C64 s = 0.5 * (xs + imu * G[(size_t)i * ld + p]);
+      X[xi] = s;
+      const C64 d = s - xs;
+      dsum += norm2(d);
+      nsum += norm2(s);
+    }
+  }
+  __shared__ double sh[2][4];
+  for (int o = 32; o > 0; o >>= 1) {
+    dsum += __shfl_xor(dsum, o, 64);
+    nsum += __shfl_xor(nsum, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = dsum;
+    sh[1][threadIdx.x >> 6] = nsum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2 + 0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2 + 1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+  }
+}
+
+// r_b = |S (S e_1) - e_1| per matrix (one workgroup per matrix)
+__global__ void __launch_bounds__(256) k_rh_resid(int ld, const int* __restrict__ nvec, const C64* __restrict__ S_b,
+                                                  double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int n = nvec[b];
+  const C64* S = S_b + (size_t)b * ld * ld;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    C64 t = mk(0.0, 0.0);
+    for (int j = 0; j < n; ++j) t = t + cmul(S[(size_t)i * ld + j], S[(size_t)j * ld]);
+    if (i == 0) t.re -= 1.0;
+    acc += norm2(t);
+  }
+  __shared__ double sh[4];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[b] = sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_rh_mu;
+DevBuf g_G0, g_G1, g_int, g_dbl, g_mu;
+}  // namespace
+
+template <int NB, int RM>
+static void launch_inverse(int batch, int ld, int maxn, const int* nvec, const int* act, C64* S, C64* G0, C64* G1,
+                           int* p2r, int* perm, double* logdet, int* sing, hipStream_t st, int* nb_out) {
+  const C64* cur = S;
+  int which = 0;
+  const int tiles = (maxn + 63) / 64;
+  for (int c0 = 0; c0 < maxn; c0 += NB) {
+    C64* nxt = which ? G1 : G0;
+    hipLaunchKernelGGL((k_gj_panel<NB, RM>), dim3(batch), dim3(PT), 0, st, ld, nvec, act, c0, cur, nxt, p2r, perm,
+                       logdet, sing);
+    hipLaunchKernelGGL((k_gj_update<NB>), dim3(tiles, tiles, batch), dim3(UT), 0, st, ld, nvec, act, c0, cur, nxt,
+                       p2r);
+    cur = nxt;
+    which ^= 1;
+  }
+  *nb_out = NB;
+}
+
+int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
+                    int* iters_host, double* resid_host, hipStream_t st, const double* mu_sched, int mu_steps) {
+  std::lock_guard<std::mutex> lock(g_rh_mu);
+  if (batch <= 0 || ld <= 0) return NK_OK;
+  if (ld > 4 * PT) {
+    set_error("Roberts-Higham: matrix size %d exceeds %d", ld, 4 * PT);
+    return NK_EINVAL;
+  }
+  const size_t mb = (size_t)batch * ld * ld * sizeof(C64);
+  const int nbl = 64;
+  if (g_G0.ensure(mb) || g_G1.ensure(mb) || g_int.ensure((size_t)batch * (2 * ld + 4) * sizeof(int)) ||
+      g_dbl.ensure((size_t)batch * (2 * nbl + 4) * sizeof(double)) || g_mu.ensure((size_t)batch * sizeof(double)))
+    return NK_ENOMEM;
+  int* nvec = g_int.as<int>();
+  int* act = nvec + batch;
+  int* sing = act + batch;
+  int* p2r = sing + batch;
+  int* perm = p2r + (size_t)batch * ld;
+  double* logdet = g_dbl.as<double>();
+  double* resid = logdet + batch;
+  double* part = resid + batch;
+  double* mu_dev = g_mu.as<double>();
+
+  int maxn = 0;
+  std::vector<int> act_h(batch), zeros(batch, 0);
+  for (int b = 0; b < batch; ++b) {
+    maxn = std::max(maxn, n_host[b]);
+    act_h[b] = n_host[b] > 0 ? 1 : 0;
+    iters_host[b] = 0;
+  }
+  NK_HIP(hipMemcpyAsync(nvec, n_host, batch * sizeof(int), hipMemcpyHostToDevice, st));
+  NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+  std::vector<double> prev(batch, INFINITY), part_h((size_t)batch * nbl * 2), mu_h(batch, 1.0);
+  for (int it = 1; it <= maxit; ++it) {
+    bool any = false;
+    for (int b = 0; b < batch; ++b) any = any || act_h[b];
+    if (!any) break;
+    NK_HIP(hipMemcpyAsync(act, act_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+    if (scaling == NK_RH_LEARNED) {
+      for (int b = 0; b < batch; ++b)
+        mu_h[b] = (mu_sched && it - 1 < mu_steps) ? mu_sched[(size_t)b * mu_steps + (it - 1)] : -1.0;
+      NK_HIP(hipMemcpyAsync(mu_dev, mu_h.data(), batch * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    hipLaunchKernelGGL(k_rh_start, dim3((maxn + 255) / 256, batch), dim3(256), 0, st, ld, batch, nvec, act, perm,
+                       logdet);
+    int nbw = 16;
+    if (ld <= PT)
+      launch_inverse<16, 1>(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing,
+                            st, &nbw);
+    else if (ld <= 2 * PT)
+      launch_inverse<16, 2>(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing,
+                            st, &nbw);
+    else
+      launch_inverse<8, 4>(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing,
+                           st, &nbw);
+    const int rs = scaling == NK_RH_LEARNED ? NK_RH_LEARNED : (scaling == NK_RH_DET ? NK_RH_DET : NK_RH_NONE);
+    hipLaunchKernelGGL(k_rh_combine, dim3(nbl, batch), dim3(256), 0, st, ld, nbw, nvec, act, g_G0.as<C64>(),
+                       g_G1.as<C64>(), S, perm, logdet, rs, mu_dev, part);
+    NK_HIP(hipGetLastError());
+    NK_HIP(hipMemcpyAsync(part_h.data(), part, part_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < batch; ++b) {
+      if (!act_h[b]) continue;
+      double d = 0.0, nn = 0.0;
+      for (int i = 0; i < nbl; ++i) {
+        d += part_h[((size_t)b * nbl + i) * 2 + 0];
+        nn += part_h[((size_t)b * nbl + i) * 2 + 1];
+      }
+      const double change = std::sqrt(d / nn);
+      iters_host[b] = it;
+      if (!(change > tol) || (change < 1e-6 && change > 0.5 * prev[b])) act_h[b] = 0;
+      prev[b] = change;
+    }
+  }
+  std::vector<int> sing_h(batch);
+  NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (resid_host) {
+    hipLaunchKernelGGL(k_rh_resid, dim3(batch), dim3(256), 0, st, ld, nvec, S, resid);
+    NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  NK_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < batch; ++b)
+    if (sing_h[b]) {
+      set_error("Roberts-Higham: singular iterate in matrix %d", b);
+      return NK_WARN_NOTCONV;
+    }
+  return NK_OK;
+}
+
+}  // namespace nk

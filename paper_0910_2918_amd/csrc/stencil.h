@@ -1,0 +1,236 @@
+// Per-site hopping term of the Wilson-Dirac operator Dw(mu) on gfx950.
+//
+// The operator (Sec. 1 of the paper names it; its explicit form is the
+// standard one with the Hasenfratz-Karsch chemical potential):
+//   Dw psi(x) = (4 + m_w) psi(x) - 1/2 hop(x),
+//   hop(x) = sum_nu e^{+mu d_{nu t}} (1 - gamma_nu) U_nu(x) psi(x + nu)
+//                 + e^{-mu d_{nu t}} (1 + gamma_nu) U_nu(x - nu)^dag psi(x - nu),
+// antiperiodic in t.  In the chiral basis (1 -/+ gamma_nu) has rank two: for
+// each nu there are unit complex numbers c0, c1 and lower spins p0, p1 with
+//   (1 - gamma_nu) psi = [h0, h1; conj(c0) h0 at spin p0, conj(c1) h1 at spin p1],
+//   h0 = psi_0 + c0 psi_p0,  h1 = psi_1 + c1 psi_p1,
+// and (1 + gamma_nu) the same with c -> -c.  So each hop multiplies only a
+// two-spin half spinor by the SU(3) link (spin projection), 2 x 9 complex
+// products instead of 4 x 9.
+#pragma once
+
+#include "nk_internal.h"
+
+namespace nk {
+
+// kernel-argument bundles of NF field pointers and temporal hop factors
+template <class R, int NF>
+struct FieldPtrs {
+  const Cx<R>* p[NF];
+};
+template <class R, int NF>
+struct FieldPtrsW {
+  Cx<R>* p[NF];
+};
+template <class R, int NF>
+struct TFac {
+  R f[NF];  // forward temporal factor
+  R b[NF];  // backward temporal factor
+};
+
+// (c0, p0, c1, p1) of the projector table; c = (CR + i CI)
+template <int NU>
+struct Proj;
+template <>
+struct Proj<0> {  // gamma_1 = [[0, -i s1], [i s1, 0]]
+  static constexpr int p0 = 3, p1 = 2, c0r = 0, c0i = 1, c1r = 0, c1i = 1;
+};
+template <>
+struct Proj<1> {  // gamma_2
+  static constexpr int p0 = 3, p1 = 2, c0r = 1, c0i = 0, c1r = -1, c1i = 0;
+};
+template <>
+struct Proj<2> {  // gamma_3
+  static constexpr int p0 = 2, p1 = 3, c0r = 0, c0i = 1, c1r = 0, c1i = -1;
+};
+template <>
+struct Proj<3> {  // gamma_4 = [[0, 1], [1, 0]]
+  static constexpr int p0 = 2, p1 = 3, c0r = -1, c0i = 0, c1r = -1, c1i = 0;
+};
+
+// (CR + i CI) z for a unit CR + i CI in {1, -1, i, -i}
+template <int CR, int CI, class R>
+__device__ __forceinline__ Cx<R> mulu(Cx<R> z) {
+  if constexpr (CI == 0) {
+    if constexpr (CR > 0) return z;
+    else return mk<R>(-z.re, -z.im);
+  } else if constexpr (CI > 0) {
+    return mk<R>(-z.im, z.re);
+  } else {
+    return mk<R>(z.im, -z.re);
+  }
+}
+
+// --- link storage -----------------------------------------------------------
+template <class R>
+struct LinksPlain {
+  const Cx<R>* U;
+  int V;
+  __device__ __forceinline__ void load(int nu, int s, Cx<R> (&u)[9]) const {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = U[(size_t)(nu * 9 + e) * V + s];
+  }
+};
+
+__device__ __forceinline__ float bf16lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// BF16 storage of the first two rows (12 reals as 6 packed complex words);
+// the rows are re-orthonormalised in FP32 and the third row is rebuilt as
+// conj(row0 x row1), which makes the link exactly special unitary again.
+struct LinksBF16 {
+  const uint32_t* U;
+  int V;
+  __device__ __forceinline__ void load(int nu, int s, Cx<float> (&u)[9]) const {
+    Cx<float> r[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      uint32_t w = U[(size_t)(nu * 6 + e) * V + s];
+      r[e] = mk<float>(bf16lo(w), bf16hi(w));
+    }
+    float n0 = norm2(r[0]) + norm2(r[1]) + norm2(r[2]);
+    float i0 = rsqrtf(n0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) r[b] = i0 * r[b];
+    Cx<float> d = cmulc(r[0], r[3]) + cmulc(r[1], r[4]) + cmulc(r[2], r[5]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) r[3 + b] = r[3 + b] - cmul(d, r[b]);
+    float n1 = norm2(r[3]) + norm2(r[4]) + norm2(r[5]);
+    float i1 = rsqrtf(n1);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) r[3 + b] = i1 * r[3 + b];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u[e] = r[e];
+    u[6] = conj(cmul(r[1], r[5]) - cmul(r[2], r[4]));
+    u[7] = conj(cmul(r[2], r[3]) - cmul(r[0], r[5]));
+    u[8] = conj(cmul(r[0], r[4]) - cmul(r[1], r[3]));
+  }
+};
+
+template <class R>
+__device__ __forceinline__ void load_spinor(const Cx<R>* __restrict__ f, int V, int s, Cx<R> (&p)[12]) {
+#pragma unroll
+  for (int c = 0; c < 12; ++c) p[c] = f[(size_t)c * V + s];
+}
+
+// Keep the accumulators materialised at this point of the program: an empty
+// asm that reads and writes them stops LLVM from sinking the arithmetic of
+// every hop below the last loads, which would keep all loaded values live at
+// once.  It emits no instruction.
+template <class R, int NF>
+__device__ __forceinline__ void pin(Cx<R> (&acc)[NF][12]) {
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[f][c].re), "+v"(acc[f][c].im));
+}
+
+// one direction nu, both hops, for NF fields at once (one link load serves all)
+template <int NU, class R, int NF, class LK>
+__device__ __forceinline__ void hop_dir(const Geom& g, int s, int coord, const LK& lk,
+                                        const Cx<R>* const (&in)[NF], const R (&cf)[NF], const R (&cb)[NF],
+                                        Cx<R> (&acc)[NF][12]) {
+  using P = Proj<NU>;
+  const int L = g.L[NU], st = g.stride[NU], V = g.V;
+  const int sf = (coord == L - 1) ? s - (L - 1) * st : s + st;
+  const int sb = (coord == 0) ? s + (L - 1) * st : s - st;
+  const R bf = (NU == 3 && coord == L - 1) ? R(-1) : R(1);
+  const R bb = (NU == 3 && coord == 0) ? R(-1) : R(1);
+  Cx<R> u[9];
+  // Each hop is scheduled on its own: letting the scheduler hoist the loads
+  // of all eight hops at once needs more than 512 registers per lane and
+  // spills to scratch.  One hop keeps 9 + 12 NF complex loads in flight.
+  __builtin_amdgcn_sched_barrier(0);
+  // forward hop: (1 - gamma) U_nu(x) psi(x + nu)
+  lk.load(NU, s, u);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Cx<R> p[12];
+    load_spinor(in[f], V, sf, p);
+    const R sc = bf * cf[f];
+    Cx<R> h0[3], h1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      h0[c] = sc * (p[c] + mulu<P::c0r, P::c0i>(p[P::p0 * 3 + c]));
+      h1[c] = sc * (p[3 + c] + mulu<P::c1r, P::c1i>(p[P::p1 * 3 + c]));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cx<R> g0 = cmul(u[a * 3 + 0], h0[0]) + cmul(u[a * 3 + 1], h0[1]) + cmul(u[a * 3 + 2], h0[2]);
+      Cx<R> g1 = cmul(u[a * 3 + 0], h1[0]) + cmul(u[a * 3 + 1], h1[1]) + cmul(u[a * 3 + 2], h1[2]);
+      acc[f][a] = acc[f][a] + g0;
+      acc[f][3 + a] = acc[f][3 + a] + g1;
+      acc[f][P::p0 * 3 + a] = acc[f][P::p0 * 3 + a] + mulu<P::c0r, -P::c0i>(g0);
+      acc[f][P::p1 * 3 + a] = acc[f][P::p1 * 3 + a] + mulu<P::c1r, -P::c1i>(g1);
+    }
+  }
+  pin<R, NF>(acc);
+  __builtin_amdgcn_sched_barrier(0);
+  // backward hop: (1 + gamma) U_nu(x - nu)^dag psi(x - nu)
+  lk.load(NU, sb, u);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    Cx<R> p[12];
+    load_spinor(in[f], V, sb, p);
+    const R sc = bb * cb[f];
+    Cx<R> h0[3], h1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      h0[c] = sc * (p[c] - mulu<P::c0r, P::c0i>(p[P::p0 * 3 + c]));
+      h1[c] = sc * (p[3 + c] - mulu<P::c1r, P::c1i>(p[P::p1 * 3 + c]));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Cx<R> g0 = cmulc(u[0 * 3 + a], h0[0]) + cmulc(u[1 * 3 + a], h0[1]) + cmulc(u[2 * 3 + a], h0[2]);
+      Cx<R> g1 = cmulc(u[0 * 3 + a], h1[0]) + cmulc(u[1 * 3 + a], h1[1]) + cmulc(u[2 * 3 + a], h1[2]);
+      acc[f][a] = acc[f][a] + g0;
+      acc[f][3 + a] = acc[f][3 + a] + g1;
+      acc[f][P::p0 * 3 + a] = acc[f][P::p0 * 3 + a] - mulu<P::c0r, -P::c0i>(g0);
+      acc[f][P::p1 * 3 + a] = acc[f][P::p1 * 3 + a] - mulu<P::c1r, -P::c1i>(g1);
+    }
+  }
+  pin<R, NF>(acc);
+}
+
+// hop(x) for NF fields; eft/ebt are the forward/backward temporal factors of
+// each field (e^{+mu}, e^{-mu} for A(mu); swapped for A(-mu) = A(mu)^dag).
+template <class R, int NF, class LK>
+__device__ __forceinline__ void hopping(const Geom& g, int s, const LK& lk, const Cx<R>* const (&in)[NF],
+                                        const R (&eft)[NF], const R (&ebt)[NF], Cx<R> (&acc)[NF][12]) {
+  int r = s;
+  const int x = r % g.L[0];
+  r /= g.L[0];
+  const int y = r % g.L[1];
+  r /= g.L[1];
+  const int z = r % g.L[2];
+  const int t = r / g.L[2];
+  R one[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    one[f] = R(1);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[f][c] = mk<R>(0, 0);
+  }
+  hop_dir<0>(g, s, x, lk, in, one, one, acc);
+  hop_dir<1>(g, s, y, lk, in, one, one, acc);
+  hop_dir<2>(g, s, z, lk, in, one, one, acc);
+  hop_dir<3>(g, s, t, lk, in, eft, ebt, acc);
+}
+
+// gamma5 sign of component c = spin*3 + colour
+__device__ __forceinline__ constexpr int g5sign(int c) { return c < 6 ? 1 : -1; }
+
+// XCD-aware block order: consecutive logical tiles stay on one XCD (the
+// hardware hands workgroup b to XCD b % 8), so neighbouring sites share an L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+}  // namespace nk

@@ -1,0 +1,320 @@
+"""ctypes binding of the C ABI in include/nk.h (marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own: all work runs in the HIP library ``libnk.so``.  Device
+buffers are torch tensors (complex128, canonical layout, on the GPU); torch
+supplies the memory and the stream.  If the library is missing, importing
+this module still works but every call raises ``NKLibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnk.so")
+
+NK_OK = 0
+NK_EINVAL = -1
+NK_ENOGAUGE = -2
+NK_ENOMEM = -3
+NK_EHIP = -4
+NK_WARN_NOTCONV = 1
+NK_WARN_BREAKDOWN = 2
+
+NK_PREC_FP64 = 0
+NK_PREC_FP32 = 1
+NK_PREC_FP32_BF16LINKS = 2
+
+NK_RH_NONE = 0
+NK_RH_DET = 1
+NK_RH_LEARNED = 2
+
+NK_TWO_PASS_AUTO = 0
+NK_TWO_PASS_ON = 1
+NK_TWO_PASS_OFF = 2
+
+# every symbol include/nk.h declares
+EXPORTS = (
+    "nk_sign_params_default",
+    "nk_lattice_create",
+    "nk_lattice_destroy",
+    "nk_gauge_set",
+    "nk_gauge_set_device",
+    "nk_apply_dw",
+    "nk_apply_dw_device",
+    "nk_apply_pair_device",
+    "nk_krylov_basis_device",
+    "nk_small_sign",
+    "nk_rh_sign",
+    "nk_sign_apply",
+    "nk_sign_apply_device",
+    "nk_last_error",
+    "nk_version",
+)
+
+
+class NKError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nk error {code}: {msg}")
+        self.code = code
+
+
+class NKLibraryMissing(RuntimeError):
+    pass
+
+
+class nk_sign_params(C.Structure):
+    _fields_ = [
+        ("m_w", C.c_double),
+        ("mu", C.c_double),
+        ("k", C.c_int32),
+        ("ell", C.c_int32),
+        ("tol", C.c_double),
+        ("nrhs", C.c_int32),
+        ("precision", C.c_int32),
+        ("rh_scaling", C.c_int32),
+        ("two_pass", C.c_int32),
+        ("est_delay", C.c_int32),
+        ("check_every", C.c_int32),
+        ("rh_maxit", C.c_int32),
+        ("rh_tol", C.c_double),
+        ("ell_per_rhs", C.POINTER(C.c_int32)),
+        ("profile", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class nk_sign_info(C.Structure):
+    _fields_ = [
+        ("k_used", C.c_int32),
+        ("ell_used", C.c_int32),
+        ("rh_iters", C.c_int32),
+        ("breakdown_step", C.c_int32),
+        ("two_pass", C.c_int32),
+        ("pad", C.c_int32),
+        ("est", C.c_double),
+        ("rh_residual", C.c_double),
+        ("t_basis_ms", C.c_double),
+        ("t_small_ms", C.c_double),
+        ("t_lift_ms", C.c_double),
+        ("t_stencil_ms", C.c_double),
+        ("t_update_ms", C.c_double),
+        ("n_stencil", C.c_int32),
+        ("n_update", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+_lib = None
+
+
+def library():
+    """Load libnk.so (once); raise NKLibraryMissing if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise NKLibraryMissing(f"{LIB_PATH} is not built; run python -m paper_0910_2918_amd.build")
+    # torch ships its own HIP runtime; load it first so that libnk.so binds to
+    # the same libamdhip64 instead of pulling a second runtime into the process
+    import torch  # noqa: F401
+
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    P = C.POINTER
+    sig = {
+        "nk_sign_params_default": (None, [P(nk_sign_params)]),
+        "nk_lattice_create": (C.c_int, [P(i32), P(vp)]),
+        "nk_lattice_destroy": (C.c_int, [vp]),
+        "nk_gauge_set": (C.c_int, [vp, vp]),
+        "nk_gauge_set_device": (C.c_int, [vp, vp, vp]),
+        "nk_apply_dw": (C.c_int, [vp, dbl, dbl, i32, vp, vp, i32]),
+        "nk_apply_dw_device": (C.c_int, [vp, dbl, dbl, i32, vp, vp, i32, vp]),
+        "nk_apply_pair_device": (C.c_int, [vp, dbl, dbl, vp, vp, vp, vp, vp]),
+        "nk_krylov_basis_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, vp, vp, P(nk_sign_info), vp]),
+        "nk_small_sign": (C.c_int, [i32, i32, i32, vp, vp, vp, P(nk_sign_params), vp, P(nk_sign_info)]),
+        "nk_rh_sign": (C.c_int, [i32, i32, P(i32), vp, i32, i32, dbl, P(i32)]),
+        "nk_sign_apply": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info)]),
+        "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
+        "nk_last_error": (C.c_char_p, []),
+        "nk_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise NKError(rc, nk_last_error())
+    return rc
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    """Device pointer of a contiguous complex128 CUDA tensor."""
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch.complex128":
+        raise ValueError("expected a contiguous complex128 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _hptr(a: np.ndarray):
+    if a.dtype != np.complex128 or not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("expected a C-contiguous complex128 array")
+    return C.c_void_p(a.ctypes.data)
+
+
+def nk_last_error() -> str:
+    return library().nk_last_error().decode()
+
+
+def nk_version() -> str:
+    return library().nk_version().decode()
+
+
+def nk_sign_params_default(**kw) -> nk_sign_params:
+    p = nk_sign_params()
+    library().nk_sign_params_default(C.byref(p))
+    for k, v in kw.items():
+        if k == "ell_per_rhs":
+            arr = (C.c_int32 * len(v))(*[int(e) for e in v])
+            p._ell_keep = arr
+            p.ell_per_rhs = C.cast(arr, C.POINTER(C.c_int32))
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def nk_lattice_create(dims) -> C.c_void_p:
+    d = (C.c_int32 * 4)(*[int(x) for x in dims])
+    h = C.c_void_p()
+    _check(library().nk_lattice_create(d, C.byref(h)))
+    return h
+
+
+def nk_lattice_destroy(h) -> None:
+    _check(library().nk_lattice_destroy(h))
+
+
+def nk_gauge_set(h, U: np.ndarray) -> None:
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    _check(library().nk_gauge_set(h, _hptr(U)))
+
+
+def nk_gauge_set_device(h, dU, stream=None) -> None:
+    _check(library().nk_gauge_set_device(h, _dptr(dU), _stream(stream)))
+
+
+def nk_apply_dw(h, m_w: float, mu: float, gamma5: bool, x: np.ndarray, nrhs: int = 1) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty_like(x)
+    _check(library().nk_apply_dw(h, m_w, mu, 1 if gamma5 else 0, _hptr(x), _hptr(y), nrhs))
+    return y
+
+
+def nk_apply_dw_device(h, m_w: float, mu: float, gamma5: bool, x, y, nrhs: int = 1, stream=None) -> None:
+    _check(library().nk_apply_dw_device(h, m_w, mu, 1 if gamma5 else 0, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+
+
+def nk_apply_pair_device(h, m_w: float, mu: float, v, w, av, adw, stream=None) -> None:
+    _check(library().nk_apply_pair_device(h, m_w, mu, _dptr(v), _dptr(w), _dptr(av), _dptr(adw), _stream(stream)))
+
+
+def nk_krylov_basis_device(h, params: nk_sign_params, x, stream=None):
+    """Returns (alpha, beta, delta, info, rc); complex arrays of length k."""
+    k = params.k
+    a = np.zeros(k, np.complex128)
+    b = np.zeros(k, np.complex128)
+    d = np.zeros(k, np.complex128)
+    info = nk_sign_info()
+    rc = _check(library().nk_krylov_basis_device(h, C.byref(params), _dptr(x), _hptr(a), _hptr(b), _hptr(d),
+                                                 C.byref(info), _stream(stream)))
+    return a, b, d, info, rc
+
+
+def nk_small_sign(k: int, ell: int, hermitian: bool, alpha, beta, delta, params: nk_sign_params | None = None):
+    """Returns (z, info, rc) for host tridiagonal coefficients (complex arrays, length k)."""
+    al = np.zeros(k, np.complex128)
+    be = np.zeros(k, np.complex128)
+    de = np.zeros(k, np.complex128)
+    al[:k] = np.asarray(alpha)[:k]
+    nb = min(len(beta), k)
+    be[:nb] = np.asarray(beta)[:nb]
+    de[:nb] = np.asarray(delta)[:nb]
+    z = np.zeros(k, np.complex128)
+    info = nk_sign_info()
+    pp = C.byref(params) if params is not None else None
+    rc = _check(library().nk_small_sign(k, ell, 1 if hermitian else 0, _hptr(al), _hptr(be), _hptr(de), pp, _hptr(z),
+                                        C.byref(info)))
+    return z, info, rc
+
+
+def nk_rh_sign(S: np.ndarray, n=None, scaling: int = NK_RH_NONE, maxit: int = 100, tol: float = 1e-13):
+    """S: (batch, ld, ld) complex128; returns (sgn S, iterations, rc)."""
+    S = np.ascontiguousarray(S, dtype=np.complex128).copy()
+    if S.ndim == 2:
+        S = S[None]
+    batch, ld, _ = S.shape
+    nn = (C.c_int32 * batch)(*([ld] * batch if n is None else [int(e) for e in n]))
+    it = (C.c_int32 * batch)()
+    rc = _check(library().nk_rh_sign(batch, ld, nn, _hptr(S), scaling, maxit, tol, it))
+    return S, np.array(list(it)), rc
+
+
+def nk_sign_apply(h, params: nk_sign_params, x: np.ndarray):
+    """Host arrays; returns (y, info, rc)."""
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty_like(x)
+    info = nk_sign_info()
+    rc = _check(library().nk_sign_apply(h, C.byref(params), _hptr(x), _hptr(y), C.byref(info)))
+    return y, info, rc
+
+
+def nk_sign_apply_device(h, params: nk_sign_params, x, y, stream=None):
+    """Device tensors; returns (info, rc)."""
+    info = nk_sign_info()
+    rc = _check(library().nk_sign_apply_device(h, C.byref(params), _dptr(x), _dptr(y), C.byref(info),
+                                               _stream(stream)))
+    return info, rc
+
+
+class Lattice:
+    """Owns a lattice handle (context manager)."""
+
+    def __init__(self, dims):
+        self.dims = tuple(int(d) for d in dims)
+        self.h = nk_lattice_create(self.dims)
+
+    def close(self):
+        if self.h is not None:
+            nk_lattice_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

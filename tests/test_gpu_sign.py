@@ -1,0 +1,197 @@
+"""End-to-end GPU parity of sgn(gamma5 Dw(mu)) x (Eqs. (3)-(6)).
+
+Three levels of agreement (FP64):
+* exact: against the spectral definition (stored 4^4 results written by
+  tests/golden/make_golden.py from the oracle, and the free-field closed form
+  at the full 16^4 volume), at a k where the Krylov error is below 1e-11:
+  relative error <= 1e-10;
+* method: against the oracle's own nested / non-nested run at the same
+  (k, l), <= max(1e-10, 10 eps_true(k));
+* properties at full size: sgn^2 = 1, |sgn x| = |x| at mu = 0, bit-identical
+  one-pass and two-pass lifts.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import latgen
+from oracle import freefield as F
+from oracle import nested as N
+from oracle import wilson as W
+from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+DIMS1 = (4, 4, 4, 4)
+
+
+def _sign(lat, x, **kw):
+    b = nk()
+    p = b.nk_sign_params_default(**kw)
+    dx = to_dev(x)
+    dy = torch_cuda().empty_like(dx)
+    info, rc = b.nk_sign_apply_device(lat.h, p, dx, dy)
+    return to_host(dy), info, rc
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    lat, u = make_lattice(DIMS1, 0.4, seed=0)
+    x = latgen.random_sources(DIMS1, 1, 0)[0]
+    yield lat, u, x
+    lat.close()
+
+
+@pytest.mark.parametrize("mu,gold", [(0.0, "sign_4x4x4x4_mu0_eps0.4.npy"), (0.3, "sign_4x4x4x4_mu0.3_eps0.4.npy")])
+@pytest.mark.parametrize("ell", [0, 100, 150])
+def test_exact_level_4x4(cfg1, mu, gold, ell):
+    lat, u, x = cfg1
+    k = 300 if mu == 0.0 else 400
+    banner(f"exact level 4^4 mu={mu} k={k} ell={ell}")
+    y, info, rc = _sign(lat, x, k=k, ell=ell, mu=mu)
+    ref = np.load(os.path.join(GOLD, gold))
+    assert rc == 0
+    assert rel(y, ref) < 1e-10
+    assert info.k_used == k and info.ell_used == ell
+
+
+@pytest.mark.parametrize("ell", [0, 60])
+def test_method_level_config1(cfg1, ell):
+    lat, u, x = cfg1
+    banner(f"method level 4^4 mu=0 k=150 ell={ell}")
+    y, info, rc = _sign(lat, x, k=150, ell=ell)
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, 0.0).reshape(-1)
+    yo, io = N.sign_apply(f, f, x, 150, ell, True)
+    ref = np.load(os.path.join(GOLD, "sign_4x4x4x4_mu0_eps0.4.npy"))
+    eps_true = rel(yo, ref)
+    assert rel(y, yo) <= max(1e-10, 10 * eps_true)
+    assert rel(y, ref) < 2 * eps_true + 1e-12
+
+
+@pytest.mark.parametrize("mu,k,ell", [(0.3, 200, 50), (0.3, 120, 0)])
+def test_method_level_nonhermitian(mu, k, ell):
+    dims = (4, 4, 2, 6)
+    banner(f"method level {dims} mu={mu} k={k} ell={ell}")
+    lat, u = make_lattice(dims, 0.6, seed=1)
+    x = latgen.random_sources(dims, 1, 1)[0]
+    y, info, rc = _sign(lat, x, k=k, ell=ell, mu=mu)
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    yo, io = N.sign_apply(f, fd, x, k, ell, False)
+    yref, _ = N.sign_apply(f, fd, x, 600, 0, False)
+    eps_true = rel(yo, yref)
+    assert rel(y, yo) <= max(1e-10, 10 * eps_true)
+    lat.close()
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_full_size_free_field_exact(mu):
+    dims = (16, 16, 16, 16)
+    banner(f"free field 16^4 exact level mu={mu}")
+    lat, _ = make_lattice(dims, 0.0, unit=True)
+    x = latgen.random_sources(dims, 1, 3)[0]
+    # l = 60 would limit the accuracy to ~1e-9 (mu = 0) / ~2e-7 (mu = 0.3)
+    y, info, rc = _sign(lat, x, k=330, ell=150, mu=mu)
+    ref = F.sign_apply_free(x, M_W, mu)
+    assert rc == 0
+    assert rel(y, ref) < 1e-10
+    lat.close()
+
+
+@pytest.fixture(scope="module")
+def big():
+    dims = (16, 16, 16, 16)
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    yield lat, x
+    lat.close()
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_full_size_sign_squared(big, mu):
+    lat, x = big
+    banner(f"16^4 eps=0.8 mu={mu}: sgn(sgn x) = x")
+    y, info, rc = _sign(lat, x, k=600, ell=120, mu=mu)
+    yy, info2, rc2 = _sign(lat, y.reshape(x.shape), k=600, ell=120, mu=mu)
+    assert rel(yy, x) < 1e-7
+    if mu == 0.0:
+        assert abs(np.linalg.norm(y) - np.linalg.norm(x)) < 1e-8 * np.linalg.norm(x)
+
+
+def test_two_pass_is_bit_identical(big):
+    lat, x = big
+    banner("16^4 mu=0.3 one-pass vs two-pass lift")
+    b = nk()
+    y1, i1, _ = _sign(lat, x, k=80, ell=20, mu=0.3, two_pass=b.NK_TWO_PASS_OFF)
+    y2, i2, _ = _sign(lat, x, k=80, ell=20, mu=0.3, two_pass=b.NK_TWO_PASS_ON)
+    assert i2.two_pass == 1 and i1.two_pass == 0
+    assert rel(y2, y1) < 1e-14
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 5e-2)])
+def test_reduced_precision_error_is_stated(big, prec, tol):
+    lat, x = big
+    banner(f"16^4 mu=0.3 precision={prec} vs FP64")
+    y64, _, _ = _sign(lat, x, k=300, ell=60, mu=0.3)
+    y, info, rc = _sign(lat, x, k=300, ell=60, mu=0.3, precision=prec)
+    err = rel(y, y64)
+    print(f"precision {prec}: relative error vs FP64 = {err:.3e}")
+    assert err < tol
+
+
+def test_multiple_sources_and_uneven_ell(cfg1):
+    lat, u, x = cfg1
+    b = nk()
+    xs = latgen.random_sources(DIMS1, 3, 5)
+    ells = [0, 30, 75]
+    banner("nrhs=3 with per-source ell")
+    p = b.nk_sign_params_default(k=200, nrhs=3, ell_per_rhs=ells)
+    dx = to_dev(xs)
+    dy = torch_cuda().empty_like(dx)
+    info, rc = b.nk_sign_apply_device(lat.h, p, dx, dy)
+    y = to_host(dy).reshape(3, -1)
+    for r in range(3):
+        yr, _, _ = _sign(lat, xs[r], k=200, ell=ells[r])
+        assert rel(y[r], yr) < 1e-14
+
+
+def test_early_stop(cfg1):
+    lat, u, x = cfg1
+    banner("4^4 early stop at tol=1e-8")
+    y, info, rc = _sign(lat, x, k=400, ell=0, tol=1e-8, check_every=25, est_delay=10)
+    ref = np.load(os.path.join(GOLD, "sign_4x4x4x4_mu0_eps0.4.npy"))
+    assert rc == 0
+    assert info.k_used < 400 and info.est < 1e-8
+    assert rel(y, ref) < 1e-6
+
+
+def test_ginsparg_wilson_on_gpu(cfg1):
+    lat, u, x = cfg1
+    banner("4^4 Ginsparg-Wilson relation of Dov")
+    g5 = np.array([1, 1, -1, -1])[None, None, None, None, :, None]
+
+    def dov(v):
+        s, _, _ = _sign(lat, v, k=300, ell=80)
+        return v + g5 * s.reshape(v.shape)
+
+    v = x
+    lhs = g5 * dov(v) + dov(g5 * v)
+    rhs = dov(g5 * dov(v))
+    assert rel(lhs, rhs) < 1e-9
+
+
+def test_invalid_parameters(cfg1):
+    lat, u, x = cfg1
+    b = nk()
+    with pytest.raises(b.NKError) as ei:
+        _sign(lat, x, k=10, ell=11)
+    assert ei.value.code == b.NK_EINVAL
+    with pytest.raises(b.NKError):
+        _sign(lat, x, k=0)
+    lat2 = b.Lattice((2, 2, 2, 2))
+    with pytest.raises(b.NKError) as ei:
+        _sign(lat2, np.ones(192, np.complex128), k=4)
+    assert ei.value.code == b.NK_ENOGAUGE
+    lat2.close()
