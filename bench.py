@@ -37,7 +37,7 @@ EPS = 0.8
 # written (2 x 192 B)
 K1_BYTES_PER_SITE = 576 + 4 * 192 + 2 * 192
 HBM_PEAK_GBS = 8000.0
-PROFILE_PMC = os.path.join(ROOT, "profiles", "k_bil1_16x16x16x16_pmc.json")
+PROFILE_PMC = os.path.join(ROOT, "profiles", "k_bil1s_16x16x16x16_pmc.json")
 
 
 def kernel_source_hash() -> str:
@@ -111,12 +111,18 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--k", type=int, default=450)
-    ap.add_argument("--ell", type=int, default=90)
+    ap.add_argument("--k", type=int, default=500)
+    ap.add_argument("--ell", type=int, default=84)
     ap.add_argument("--kref-extra", type=int, default=500)
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--target", type=float, default=1e-8)
+    ap.add_argument("--probe", action="store_true",
+                    help="short run for hardware counters: a copy kernel of known size (1 GiB read, 1 GiB "
+                         "written, larger than the 256 MB Infinity Cache) three times, then one application "
+                         "at k=20, l=5 of the same workload (same stencil dispatches as the timed run)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="print the relative error of plain and nested runs over a grid of (k, l)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -143,6 +149,39 @@ def main() -> int:
 
     def params(k, ell, profile=0):
         return nk.nk_sign_params_default(k=k, ell=ell, mu=MU, m_w=M_W, profile=profile)
+
+    if args.probe:
+        n = 1024 * 1024 * 1024 // 16
+        src = torch.ones(n, dtype=torch.complex128, device=dev)
+        dst = torch.empty_like(src)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        times = []
+        for _ in range(3):
+            ev[0].record()
+            torch.mul(src, 2.0, out=dst)
+            ev[1].record()
+            torch.cuda.synchronize()
+            times.append(ev[0].elapsed_time(ev[1]))
+        nk.nk_sign_apply_device(lat.h, params(20, 5), x, y)
+        torch.cuda.synchronize()
+        gbs = 2 * n * 16 / (min(times) / 1e3) / 1e9
+        print(json.dumps({"probe": "done", "copy_bytes_read": n * 16, "copy_bytes_written": n * 16,
+                          "copy_ms": times, "copy_GBps": gbs}))
+        lat.close()
+        return 0
+
+    if args.calibrate:
+        kref = 1400
+        nk.nk_sign_apply_device(lat.h, params(kref, 0), x, yref)
+        for k in range(350, 651, 25):
+            nk.nk_sign_apply_device(lat.h, params(k, 0), x, y)
+            row = {"k": k, "plain": rel(y, yref)}
+            for ell in (k // 10, k // 8, k // 6, k // 5, k // 4):
+                nk.nk_sign_apply_device(lat.h, params(k, ell), x, y)
+                row[f"l={ell}"] = rel(y, yref)
+            print(json.dumps(row), flush=True)
+        lat.close()
+        return 0
 
     # accuracy, untimed: reference = non-nested at k + kref_extra
     kref = args.k + args.kref_extra
@@ -223,7 +262,7 @@ def main() -> int:
         "rh_iters": rh_iters,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_bil1 (fused A v, A^dag w two-sided Lanczos stencil step, FP64)",
+            "kernel": "k_bil1s (fused A v, A^dag w two-sided Lanczos stencil step, FP64)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -329,13 +329,8 @@ int nk_lattice_create(const int32_t dims[4], nk_lattice** out) {
     return NK_EINVAL;
   }
   nk_lattice* lat = new nk_lattice();
-  lat->g.V = (int)V;
-  int st = 1;
-  for (int i = 0; i < 4; ++i) {
-    lat->g.L[i] = dims[i];
-    lat->g.stride[i] = st;
-    st *= dims[i];
-  }
+  const int d4[4] = {dims[0], dims[1], dims[2], dims[3]};
+  geom_init(lat->g, d4);
   if (hipGetDevice(&lat->device) != hipSuccess) {
     (void)hipGetLastError();
     delete lat;

@@ -12,11 +12,20 @@
 // same fixed order, so every workgroup sees bit-identical coefficients and no
 // floating-point atomics are used.  Coefficients never leave the device during
 // the recurrence.
+#include <hip/hip_ext.h>
+
 #include "stencil.h"
 
 namespace nk {
 
 constexpr int NT = 256;
+
+#ifndef NK_SPLIT_PAIR
+#define NK_SPLIT_PAIR 1  // 0: one lane per site (both fields); 1: two lanes per site (one per field)
+#endif
+#ifndef NK_FIELD_MAJOR
+#define NK_FIELD_MAJOR 0  // with NK_SPLIT_PAIR: the first half of the grid applies A to v, the second A^dag to w
+#endif
 
 template <int NQ>
 __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
@@ -245,6 +254,95 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
   }
 }
 
+// The same step with two lanes per site: the even lane computes A v_j, the
+// odd lane A^dag w_j.  Both lanes read the same link addresses in the same
+// instruction (one memory request), each lane needs half the registers of
+// the two-field version, and twice as many waves are in flight -- at 16^4 the
+// one-lane version leaves a single wave per SIMD to hide all load latency.
+template <class R, class LK>
+__global__ void __launch_bounds__(NT) k_bil1s(Geom g, LK lk, R diag, R eft, R ebt, int j,
+                                              const Cx<R>* __restrict__ vj, const Cx<R>* __restrict__ wj,
+                                              const Cx<R>* __restrict__ vjm1, const Cx<R>* __restrict__ wjm1,
+                                              Cx<R>* __restrict__ p, Cx<R>* __restrict__ q,
+                                              const double* __restrict__ partIn, int nbIn,
+                                              double* __restrict__ partOut, Coefs c) {
+  if (c.flags[0]) return;
+  double red[4];
+  reduce_partials<4>(partIn, nbIn, red);
+  const C64 sdot = mk(red[0], red[1]);
+  const double sabs = sqrt(norm2(sdot));
+  if (j == 0 && !(sabs > 0.0 && sabs < 1e300)) {  // zero or non-finite source
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[0] = -1;
+    return;
+  }
+  if (j > 0 && !(sabs > 1e-14 * sqrt(red[2] * red[3]))) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[0] = j;
+    return;
+  }
+  const double delta = sqrt(sabs);
+  const C64 beta = (1.0 / delta) * sdot;
+  const double svj = 1.0 / delta;
+  const C64 swj = (1.0 / norm2(beta)) * beta;  // 1 / conj(beta)
+  double svjm1 = 0.0;
+  C64 swjm1 = mk(0.0, 0.0);
+  if (j > 0) {
+    svjm1 = c.sv[j - 1];
+    swjm1 = c.sw[j - 1];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c.sv[j] = svj;
+    c.sw[j] = swj;
+    if (j > 0) {
+      c.beta[j - 1] = beta;
+      c.delta[j - 1] = mk(delta, 0.0);
+    }
+  }
+#if NK_FIELD_MAJOR
+  const int half = gridDim.x >> 1;
+  const int f = blockIdx.x >= half ? 1 : 0;  // 0: A v_j, 1: A^dag w_j
+  int hb = blockIdx.x - f * half;
+  if ((half & 7) == 0) hb = (hb & 7) * (half >> 3) + (hb >> 3);
+  const int s = hb * NT + threadIdx.x;
+#else
+  const int f = threadIdx.x & 1;  // 0: A v_j, 1: A^dag w_j
+  const int s = xcd_block() * (NT / 2) + (threadIdx.x >> 1);
+#endif
+  const C64 scale = f ? swj : mk(svj, 0.0);
+  const C64 sub = f ? delta * swjm1 : svjm1 * beta;  // delta_{j-1} sw_{j-1} or beta_{j-1} sv_{j-1}
+  const Cx<R>* in = f ? wj : vj;
+  const Cx<R>* prev = f ? wjm1 : vjm1;
+  Cx<R>* out = f ? q : p;
+  double dre = 0.0, dim = 0.0;
+  if (s < g.V) {
+    Cx<R> acc[1][12];
+    const Cx<R>* ins[1] = {in};
+    const R ef[1] = {f ? ebt : eft};
+    const R eb[1] = {f ? eft : ebt};
+    hopping<R, 1>(g, s, lk, ins, ef, eb, acc);
+#pragma unroll
+    for (int cc = 0; cc < 12; ++cc) {
+      const size_t i = (size_t)cc * g.V + s;
+      Cx<R> a = diag * in[i] - R(0.5) * acc[0][cc];
+      if (cc >= 6) a = mk<R>(-a.re, -a.im);
+      const C64 ad = widen(a);
+      C64 o = cmul(scale, ad);
+      if (j > 0) o = o - cmul(sub, widen(prev[i]));
+      out[i] = narrow<R>(o);
+      if (f == 0) {
+        const C64 t = cmulc(widen(wj[i]), ad);
+        dre += t.re;
+        dim += t.im;
+      }
+    }
+  }
+  double v[2] = {dre, dim};
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    partOut[blockIdx.x] = v[0];
+    partOut[gridDim.x + blockIdx.x] = v[1];
+  }
+}
+
 // two-sided Lanczos, K2: alpha_j = conj(sw_j) sv_j (w~_j^dag A v~_j);
 //   v_hat = p - alpha_j v_j,  w_hat = q - conj(alpha_j) w_j,
 // partial sums of s = w_hat^dag v_hat, |v_hat|^2, |w_hat|^2.
@@ -266,18 +364,39 @@ __global__ void __launch_bounds__(NT) k_bil2(int n, int j, const Cx<R>* __restri
   const bool acc = lift.y && (j + 1 < lift.kused);
   const C64 lcn = acc ? lift.lc[j + 1] : mk(0.0, 0.0);
   double sre = 0.0, sim = 0.0, nv = 0.0, nw = 0.0;
-  for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-    const Cx<R> vr = narrow<R>(widen(p[i]) - cmul(av, widen(vj[i])));
-    const Cx<R> wr = narrow<R>(widen(q[i]) - cmul(aw, widen(wj[i])));
-    vnext[i] = vr;
-    wnext[i] = wr;
-    const C64 vd = widen(vr), wd = widen(wr);
-    const C64 t = cmulc(wd, vd);
-    sre += t.re;
-    sim += t.im;
-    nv += norm2(vd);
-    nw += norm2(wd);
-    if (acc) lift.y[i] = lift.y[i] + cmul(lcn, vd);
+  // four elements per thread and iteration: all loads are issued before the
+  // first store, which keeps enough bytes in flight to stream at full rate
+  constexpr int U = 4;
+  const int stride = gridDim.x * NT;
+  for (int i0 = blockIdx.x * NT + threadIdx.x; i0 < n; i0 += U * stride) {
+    Cx<R> pp[U], qq[U], vv[U], ww[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * stride;
+      if (i < n) {
+        pp[u] = p[i];
+        qq[u] = q[i];
+        vv[u] = vj[i];
+        ww[u] = wj[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * stride;
+      if (i < n) {
+        const Cx<R> vr = narrow<R>(widen(pp[u]) - cmul(av, widen(vv[u])));
+        const Cx<R> wr = narrow<R>(widen(qq[u]) - cmul(aw, widen(ww[u])));
+        vnext[i] = vr;
+        wnext[i] = wr;
+        const C64 vd = widen(vr), wd = widen(wr);
+        const C64 t = cmulc(wd, vd);
+        sre += t.re;
+        sim += t.im;
+        nv += norm2(vd);
+        nw += norm2(wd);
+        if (acc) lift.y[i] = lift.y[i] + cmul(lcn, vd);
+      }
+    }
   }
   double v[4] = {sre, sim, nv, nw};
   block_sum<4>(v);
@@ -352,7 +471,7 @@ static int get_buffers(nk_lattice* lat, const BasisPlan& bp, void* vk_ext, Basis
   b.q = w + b.colbytes;
   b.wring = w + 2 * b.colbytes;
   b.vk = bp.store ? (char*)vk_ext : w + 4 * b.colbytes;
-  const int nb1 = (g.V + NT - 1) / NT, nb2 = nb_elem(g);
+  const int nb1 = 2 * ((g.V + NT - 1) / NT) + 1, nb2 = nb_elem(g);
   const int nbmax = nb1 > nb2 ? nb1 : nb2;
   if (lat->part.ensure((size_t)2 * 4 * nbmax * sizeof(double))) return NK_ENOMEM;
   b.partA = lat->part.as<double>();
@@ -395,6 +514,8 @@ static int run_steps(nk_lattice* lat, const BasisPlan& bp, const LK& lk, const C
   const Geom& g = lat->g;
   const int n = 12 * g.V;
   const int nb1 = (g.V + NT - 1) / NT, nb2 = nb_elem(g);
+  // two lanes per site; in field-major order each half of the grid covers all sites
+  const int nb1s = NK_FIELD_MAJOR ? 2 * ((g.V + NT - 1) / NT) : (2 * g.V + NT - 1) / NT;
   const R diag = (R)(4.0 + bp.m_w);
   auto col = [&](int j) -> Cx<R>* {
     const int s = bp.store ? j : (j % 3);
@@ -410,36 +531,42 @@ static int run_steps(nk_lattice* lat, const BasisPlan& bp, const LK& lk, const C
       hipLaunchKernelGGL((k_start<R, 4>), dim3(nb2), dim3(NT), 0, st, n, x, col(0), wsl(0), b.partB, lift);
     NK_HIP(hipGetLastError());
   }
-  // K1 reads the partial sums of the previous K2 (or of k_start), both nb2 wide
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  auto mark = [&](hipEvent_t* e) -> int {
-    if (!bp.profile) return NK_OK;
-    if (int r = prof_event(lat, e)) return r;
-    NK_HIP(hipEventRecord(*e, st));
-    return NK_OK;
-  };
+  // K1 reads the partial sums of the previous K2 (or of k_start), both nb2 wide.
+  // When profiling, each launch carries its own start/stop events: the runtime
+  // stamps them from the dispatch packet itself, so the elapsed time is the
+  // kernel's execution and excludes queueing gaps between launches.
   for (int j = j0; j < j1; ++j) {
     for (int kind = 0; kind < 2; ++kind) {
-      if (int r = mark(&e0)) return r;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (bp.profile) {
+        if (int r = prof_event(lat, &e0)) return r;
+        if (int r = prof_event(lat, &e1)) return r;
+      }
       if (bp.hermitian) {
         if (kind == 0)
-          hipLaunchKernelGGL((k_lan1<R, LK>), dim3(nb1), dim3(NT), 0, st, g, lk, diag, j, col(j),
-                             j > 0 ? col(j - 1) : col(j), p, b.partB, nb2, b.partA, c);
+          hipExtLaunchKernelGGL((k_lan1<R, LK>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, j, col(j),
+                                j > 0 ? col(j - 1) : col(j), p, b.partB, nb2, b.partA, c);
         else
-          hipLaunchKernelGGL((k_lan2<R>), dim3(nb2), dim3(NT), 0, st, n, j, p, col(j), col(j + 1), b.partA, nb1,
-                             b.partB, c, lift);
+          hipExtLaunchKernelGGL((k_lan2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, col(j), col(j + 1),
+                                b.partA, nb1, b.partB, c, lift);
       } else {
         const R eft = (R)exp(bp.mu), ebt = (R)exp(-bp.mu);
-        if (kind == 0)
-          hipLaunchKernelGGL((k_bil1<R, LK>), dim3(nb1), dim3(NT), 0, st, g, lk, diag, eft, ebt, j, col(j),
-                             wsl(j), j > 0 ? col(j - 1) : col(j), j > 0 ? wsl(j - 1) : wsl(j), p, q, b.partB, nb2,
-                             b.partA, c);
-        else
-          hipLaunchKernelGGL((k_bil2<R>), dim3(nb2), dim3(NT), 0, st, n, j, p, q, col(j), wsl(j), col(j + 1),
-                             wsl(j + 1), b.partA, nb1, b.partB, c, lift);
+        const int nbk1 = NK_SPLIT_PAIR ? nb1s : nb1;
+        if (kind == 0) {
+          if (NK_SPLIT_PAIR)
+            hipExtLaunchKernelGGL((k_bil1s<R, LK>), dim3(nb1s), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j,
+                                  col(j), wsl(j), j > 0 ? col(j - 1) : col(j), j > 0 ? wsl(j - 1) : wsl(j), p, q,
+                                  b.partB, nb2, b.partA, c);
+          else
+            hipExtLaunchKernelGGL((k_bil1<R, LK>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j,
+                                  col(j), wsl(j), j > 0 ? col(j - 1) : col(j), j > 0 ? wsl(j - 1) : wsl(j), p, q,
+                                  b.partB, nb2, b.partA, c);
+        } else {
+          hipExtLaunchKernelGGL((k_bil2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, q, col(j), wsl(j),
+                                col(j + 1), wsl(j + 1), b.partA, nbk1, b.partB, c, lift);
+        }
       }
       NK_HIP(hipGetLastError());
-      if (int r = mark(&e1)) return r;
       if (bp.profile) lat->evkind.push_back(kind);
     }
   }

@@ -10,14 +10,27 @@ __device__ __forceinline__ uint32_t f2bf16(float f) {
   return b >> 16;
 }
 
-// canonical U[site][nu][a][b] -> U64/U32 [(nu*9 + a*3 + b) * V + site], Ubf [(nu*6 + e) * V + site]
-__global__ void k_pack_gauge(int V, const C64* __restrict__ canon, C64* __restrict__ u64, C32* __restrict__ u32,
+// device index of canonical site s
+__device__ __forceinline__ int dev_site(const Geom& g, int s) {
+  const int x = s % g.L[0];
+  int r = s / g.L[0];
+  const int y = r % g.L[1];
+  r /= g.L[1];
+  const int z = r % g.L[2];
+  const int t = r / g.L[2];
+  return tiled_index(g, x, y, z, t);
+}
+
+// canonical U[site][nu][a][b] -> U64/U32 [(nu*9 + a*3 + b) * V + dsite], Ubf [(nu*6 + e) * V + dsite]
+__global__ void k_pack_gauge(Geom g, const C64* __restrict__ canon, C64* __restrict__ u64, C32* __restrict__ u32,
                              uint32_t* __restrict__ ubf) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= V) return;
+  const int V = g.V;
+  const int sc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sc >= V) return;
+  const int s = dev_site(g, sc);
   for (int nu = 0; nu < 4; ++nu) {
     for (int e = 0; e < 9; ++e) {
-      C64 v = canon[(size_t)s * 36 + nu * 9 + e];
+      C64 v = canon[(size_t)sc * 36 + nu * 9 + e];
       u64[(size_t)(nu * 9 + e) * V + s] = v;
       u32[(size_t)(nu * 9 + e) * V + s] = narrow<float>(v);
       if (e < 6) ubf[(size_t)(nu * 6 + e) * V + s] = f2bf16((float)v.re) | (f2bf16((float)v.im) << 16);
@@ -26,19 +39,47 @@ __global__ void k_pack_gauge(int V, const C64* __restrict__ canon, C64* __restri
 }
 
 template <class R>
-__global__ void k_pack_spinor(int V, const C64* __restrict__ canon, Cx<R>* __restrict__ dev) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= V) return;
+__global__ void k_pack_spinor(Geom g, const C64* __restrict__ canon, Cx<R>* __restrict__ dev) {
+  const int sc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sc >= g.V) return;
+  const int s = dev_site(g, sc);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) dev[(size_t)c * V + s] = narrow<R>(canon[(size_t)s * 12 + c]);
+  for (int c = 0; c < 12; ++c) dev[(size_t)c * g.V + s] = narrow<R>(canon[(size_t)sc * 12 + c]);
 }
 
 template <class R>
-__global__ void k_unpack_spinor(int V, const Cx<R>* __restrict__ dev, C64* __restrict__ canon) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= V) return;
+__global__ void k_unpack_spinor(Geom g, const Cx<R>* __restrict__ dev, C64* __restrict__ canon) {
+  const int sc = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sc >= g.V) return;
+  const int s = dev_site(g, sc);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) canon[(size_t)s * 12 + c] = widen(dev[(size_t)c * V + s]);
+  for (int c = 0; c < 12; ++c) canon[(size_t)sc * 12 + c] = widen(dev[(size_t)c * g.V + s]);
+}
+
+void geom_init(Geom& g, const int dims[4]) {
+  int st = 1;
+  g.V = 1;
+  for (int d = 0; d < 4; ++d) {
+    g.L[d] = dims[d];
+    g.stride[d] = st;
+    st *= dims[d];
+    g.V *= dims[d];
+    g.b[d] = (dims[d] % 4 == 0) ? 4 : 2;
+    g.lb[d] = g.b[d] == 4 ? 2 : 1;
+    g.nt[d] = dims[d] / g.b[d];
+  }
+  int ls = 1, lts = 0;
+  for (int d = 0; d < 4; ++d) {
+    g.lstr[d] = ls;
+    ls *= g.b[d];
+    lts += g.lb[d];
+  }
+  g.lts = lts;
+  int ts = 1 << lts;
+  for (int d = 0; d < 4; ++d) {
+    g.tstr[d] = ts;
+    ts *= g.nt[d];
+  }
 }
 
 int pack_gauge(nk_lattice* lat, const C64* canon, hipStream_t st) {
@@ -46,7 +87,7 @@ int pack_gauge(nk_lattice* lat, const C64* canon, hipStream_t st) {
   if (lat->U64.ensure((size_t)36 * V * sizeof(C64)) || lat->U32.ensure((size_t)36 * V * sizeof(C32)) ||
       lat->Ubf.ensure((size_t)24 * V * sizeof(uint32_t)))
     return NK_ENOMEM;
-  hipLaunchKernelGGL(k_pack_gauge, dim3((V + 255) / 256), dim3(256), 0, st, V, canon, lat->U64.as<C64>(),
+  hipLaunchKernelGGL(k_pack_gauge, dim3((V + 255) / 256), dim3(256), 0, st, lat->g, canon, lat->U64.as<C64>(),
                      lat->U32.as<C32>(), lat->Ubf.as<uint32_t>());
   NK_HIP(hipGetLastError());
   return NK_OK;
@@ -54,14 +95,14 @@ int pack_gauge(nk_lattice* lat, const C64* canon, hipStream_t st) {
 
 template <class R>
 int pack_spinor(const Geom& g, const C64* canon, Cx<R>* dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_spinor<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g.V, canon, dev);
+  hipLaunchKernelGGL(k_pack_spinor<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g, canon, dev);
   NK_HIP(hipGetLastError());
   return NK_OK;
 }
 
 template <class R>
 int unpack_spinor(const Geom& g, const Cx<R>* dev, C64* canon, hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack_spinor<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g.V, dev, canon);
+  hipLaunchKernelGGL(k_unpack_spinor<R>, dim3((g.V + 255) / 256), dim3(256), 0, st, g, dev, canon);
   NK_HIP(hipGetLastError());
   return NK_OK;
 }

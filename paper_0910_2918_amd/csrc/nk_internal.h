@@ -55,18 +55,45 @@ template <class R>
 __host__ __device__ __forceinline__ Cx<R> narrow(Cx<double> a) { return mk<R>((R)a.re, (R)a.im); }
 
 // ---------------------------------------------------------------------------
-// lattice geometry: dims {Lx, Ly, Lz, Lt}, site = ((t Lz + z) Ly + y) Lx + x
+// lattice geometry: dims {Lx, Ly, Lz, Lt}.
+// Canonical (API) site order: ((t Lz + z) Ly + y) Lx + x.
+// Device site order is tiled: the lattice is cut into tiles of b0 x b1 x b2 x b3
+// sites (b = 4 where the extent allows, else 2) and
+//   site = tile * TS + local,  local = ((tl b2 + zl) b1 + yl) b0 + xl,
+//   tile = ((TT n2 + TZ) n1 + TY) n0 + TX,
+// so that one workgroup's sites form a compact hypercube whose neighbours
+// mostly lie in the same tile (and in cache).
 struct Geom {
   int L[4];
-  int stride[4];  // 1, Lx, Lx Ly, Lx Ly Lz
+  int stride[4];  // canonical strides 1, Lx, Lx Ly, Lx Ly Lz
   int V;
+  int b[4];       // tile extent per direction
+  int lb[4];      // log2 b
+  int lstr[4];    // local strides within a tile
+  int nt[4];      // tiles per direction
+  int tstr[4];    // site offset between neighbouring tiles in each direction
+  int lts;        // log2 of the tile size TS
 };
 
+void geom_init(Geom& g, const int dims[4]);
+
+// device index of the site with coordinates (x, y, z, t)
+__host__ __device__ __forceinline__ int tiled_index(const Geom& g, int x, int y, int z, int t) {
+  const int c[4] = {x, y, z, t};
+  int tile = 0, loc = 0;
+#pragma unroll
+  for (int d = 3; d >= 0; --d) {
+    tile = tile * g.nt[d] + (c[d] >> g.lb[d]);
+    loc = (loc << g.lb[d]) | (c[d] & (g.b[d] - 1));
+  }
+  return (tile << g.lts) + loc;
+}
+
 // device spinor layout: component c = spin*3 + colour is a contiguous array
-// of V complex numbers: field[c * V + site].  Krylov vectors live in this
-// layout; only pack/unpack see the canonical site-major order.
+// of V complex numbers: field[c * V + site] (tiled site order).  Krylov
+// vectors live in this layout; only pack/unpack see the canonical order.
 // device link layout: U[(nu * 9 + a * 3 + b) * V + site] (FP64 / FP32), or
-// for BF16 storage Ub[(nu * 12 + r) * V + site], r = the 12 reals of rows 0, 1.
+// for BF16 storage Ub[(nu * 6 + e) * V + site], e = the 6 complex entries of rows 0, 1.
 
 // ---------------------------------------------------------------------------
 // error state

@@ -325,6 +325,179 @@ __global__ void __launch_bounds__(256) k_rh_resid(int ld, const int* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Small matrices (n <= 128): one 512-thread workgroup per matrix runs every
+// Roberts-Higham iteration in a single launch, with the matrix being inverted
+// in registers.  With nseg = floor(512 / n) row segments of rps = ceil(n / nseg)
+// rows, thread tid owns column c = tid % n and rows r0 .. r0 + rps - 1 of
+// segment tid / n (r0 = segment * rps); rps <= SQ.  Per pivot column t:
+//   * the owners of column t copy it to LDS; every wave then finds the pivot
+//     redundantly (largest unused row r_t, ties to the smaller row), so no
+//     extra barrier is needed;
+//   * the owner of (r_t, c) writes the scaled pivot row to LDS;
+//   * every element updates from two LDS reads: the multiplier of its row
+//     (a wave-wide broadcast) and the pivot-row value of its column.
+// Rows are never moved: inv[pos(r)][r_c] is the element held at (r, c).
+// LDS buffers are double-buffered by t, two barriers per pivot.  The
+// iterates stay in the caller's global buffer and the stopping test runs in
+// the kernel, so there is no host round trip per iteration.
+constexpr int ST_RH = 512;  // threads: 128 columns x 4 row segments (256-register budget per lane)
+constexpr int SMAX = 128;
+
+__device__ __forceinline__ unsigned long long piv_key(double v, int r) {
+  // larger |value| wins, then the smaller row index
+  const float fv = (float)v;
+  return ((unsigned long long)__float_as_uint(fv) << 32) | (unsigned)(0x7fffffff - r);
+}
+
+template <int SQ>  // rows per thread; n <= 4 SQ
+__global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restrict__ nvec, C64* __restrict__ S_b,
+                                                   int scaling, const double* __restrict__ mu_sched, int mu_steps,
+                                                   int maxit, double tol, int* __restrict__ iters,
+                                                   int* __restrict__ sing) {
+  const int b = blockIdx.x;
+  const int n = nvec[b];
+  if (n <= 0) {
+    if (threadIdx.x == 0) iters[b] = 0;
+    return;
+  }
+  C64* S = S_b + (size_t)b * ld * ld;
+  __shared__ C64 s_col[2][SMAX];
+  __shared__ C64 s_row[2][SMAX];
+  __shared__ int s_used[SMAX];
+  __shared__ int s_rowof[SMAX];  // pivot row of column t
+  __shared__ int s_pos[SMAX];    // column whose pivot row is r
+  __shared__ double s_red[2][ST_RH / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int nseg = ST_RH / n;
+  const int rps = (n + nseg - 1) / nseg;  // <= SQ (checked by the host)
+  const int c = tid % n;
+  const int seg = tid / n;
+  const int r0 = seg * rps;
+  const int rend = min(n, r0 + rps);  // rows r0 .. rend - 1
+  const bool colok = seg < nseg;
+  C64 a[SQ];
+  double prev = INFINITY;
+  int it = 0, bad = 0;
+  for (it = 1; it <= maxit; ++it) {
+    // a per-iteration copy of the base pointer that the compiler cannot see
+    // through: otherwise it hoists SQ 64-bit element addresses out of the
+    // iteration loop and keeps them live through every pivot step
+    C64* Si = S;
+    int base = r0 * ld + c;  // n <= 128 and ld <= 128: 32-bit offsets suffice
+    asm volatile("" : "+s"(Si), "+v"(base));
+#pragma unroll
+    for (int q = 0; q < SQ; ++q) {
+      a[q] = (colok && r0 + q < rend) ? Si[base + q * ld] : mk(0.0, 0.0);
+      if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int r = tid; r < n; r += ST_RH) s_used[r] = 0;
+    double logdet = 0.0;
+    __syncthreads();
+    for (int t = 0; t < n; ++t) {
+      const int par = t & 1;
+      if (colok && c == t) {
+#pragma unroll
+        for (int q = 0; q < SQ; ++q)
+          if (r0 + q < rend) s_col[par][r0 + q] = a[q];
+      }
+      __syncthreads();
+      unsigned long long key = 0;
+      for (int r = lane; r < n; r += 64)
+        if (!s_used[r]) {
+          const C64 v = s_col[par][r];
+          const unsigned long long kk = piv_key(fabs(v.re) + fabs(v.im), r);
+          key = kk > key ? kk : key;
+        }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long ok = __shfl_xor(key, o, 64);
+        key = ok > key ? ok : key;
+      }
+      const int pr = 0x7fffffff - (int)(key & 0xffffffffu);
+      const C64 pv = s_col[par][pr];
+      if (!(fabs(pv.re) + fabs(pv.im) > 0.0)) bad = 1;
+      const C64 d = cinv(pv);
+      if (scaling != NK_RH_NONE) logdet += 0.5 * log(norm2(pv));
+      if (colok && pr >= r0 && pr < rend) {
+        C64 v = a[0];
+#pragma unroll
+        for (int q = 1; q < SQ; ++q)
+          if (pr - r0 == q) v = a[q];
+        s_row[par][c] = (c == t) ? d : cmul(v, d);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        s_used[pr] = 1;
+        s_rowof[t] = pr;
+        s_pos[pr] = t;
+      }
+      const C64 rv = s_row[par][c];
+      const bool ct = c == t;
+      // rows past rend read stale LDS entries; their values are never used
+      // branch-free so that the LDS reads of a chunk are issued together
+#pragma unroll
+      for (int q = 0; q < SQ; ++q) {
+        const C64 f = s_col[par][min(r0 + q, SMAX - 1)];
+        const C64 base = ct ? mk(0.0, 0.0) : a[q];
+        const C64 upd = base - cmul(f, rv);
+        a[q] = (r0 + q == pr) ? rv : upd;
+        if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);  // bound the hoisted LDS reads
+      }
+    }
+    __syncthreads();
+    // S_{n+1} = (mu S_n + (mu S_n)^{-1}) / 2, inv[pos(r)][rowof(c)] held at (r, c)
+    double mu = 1.0;
+    if (scaling == NK_RH_DET) mu = exp(-logdet / n);
+    if (scaling == NK_RH_LEARNED) {
+      const double m = (mu_sched && it - 1 < mu_steps) ? mu_sched[(size_t)b * mu_steps + (it - 1)] : -1.0;
+      mu = m > 0.0 ? m : exp(-logdet / n);
+    }
+    const double imu = 1.0 / mu;
+    double dsum = 0.0, nsum = 0.0;
+    if (colok) {
+      const int j = s_rowof[c];
+#pragma unroll
+      for (int q = 0; q < SQ; ++q) {
+        if (r0 + q < rend) {
+          const int xi = s_pos[r0 + q] * ld + j;
+          const C64 xs = mu * S[xi];
+          const C64 sn = 0.5 * (xs + imu * a[q]);
+          S[xi] = sn;
+          dsum += norm2(sn - xs);
+          nsum += norm2(sn);
+        }
+        if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      dsum += __shfl_xor(dsum, o, 64);
+      nsum += __shfl_xor(nsum, o, 64);
+    }
+    if (lane == 0) {
+      s_red[0][wid] = dsum;
+      s_red[1][wid] = nsum;
+    }
+    __syncthreads();
+    dsum = 0.0;
+    nsum = 0.0;
+#pragma unroll
+    for (int w = 0; w < ST_RH / 64; ++w) {
+      dsum += s_red[0][w];
+      nsum += s_red[1][w];
+    }
+    const double change = sqrt(dsum / nsum);
+    __syncthreads();
+    if (bad || !(change > tol) || (change < 1e-6 && change > 0.5 * prev)) break;
+    prev = change;
+  }
+  if (tid == 0) {
+    iters[b] = it > maxit ? maxit : it;
+    if (bad) sing[b] = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 namespace {
 std::mutex g_rh_mu;
 DevBuf g_G0, g_G1, g_int, g_dbl, g_mu;
@@ -373,6 +546,42 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
 
   int maxn = 0;
   std::vector<int> act_h(batch), zeros(batch, 0);
+  for (int b = 0; b < batch; ++b) maxn = std::max(maxn, n_host[b]);
+  if (maxn <= SMAX) {
+    NK_HIP(hipMemcpyAsync(nvec, n_host, batch * sizeof(int), hipMemcpyHostToDevice, st));
+    NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+    const double* mdev = nullptr;
+    if (scaling == NK_RH_LEARNED && mu_sched && mu_steps > 0) {
+      if (g_mu.ensure((size_t)batch * mu_steps * sizeof(double))) return NK_ENOMEM;
+      NK_HIP(hipMemcpyAsync(g_mu.p, mu_sched, (size_t)batch * mu_steps * sizeof(double), hipMemcpyHostToDevice, st));
+      mdev = g_mu.as<double>();
+    }
+    int rps = 0;  // largest rows-per-thread over the batch
+    for (int b = 0; b < batch; ++b)
+      if (n_host[b] > 0) rps = std::max(rps, (n_host[b] + ST_RH / n_host[b] - 1) / (ST_RH / n_host[b]));
+    if (rps <= 16)
+      hipLaunchKernelGGL(k_rh_small<16>, dim3(batch), dim3(ST_RH), 0, st, ld, nvec, S, scaling, mdev, mu_steps, maxit,
+                         tol, act, sing);
+    else
+      hipLaunchKernelGGL(k_rh_small<32>, dim3(batch), dim3(ST_RH), 0, st, ld, nvec, S, scaling, mdev, mu_steps, maxit,
+                         tol, act, sing);
+    NK_HIP(hipGetLastError());
+    std::vector<int> sing_h(batch);
+    NK_HIP(hipMemcpyAsync(iters_host, act, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+    if (resid_host) {
+      hipLaunchKernelGGL(k_rh_resid, dim3(batch), dim3(256), 0, st, ld, nvec, S, resid);
+      NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    NK_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < batch; ++b)
+      if (sing_h[b]) {
+        set_error("Roberts-Higham: singular iterate in matrix %d", b);
+        return NK_WARN_NOTCONV;
+      }
+    return NK_OK;
+  }
+  maxn = 0;
   for (int b = 0; b < batch; ++b) {
     maxn = std::max(maxn, n_host[b]);
     act_h[b] = n_host[b] > 0 ? 1 : 0;

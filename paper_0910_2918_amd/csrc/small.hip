@@ -30,32 +30,47 @@ __device__ __forceinline__ C64 cdiv(C64 a, C64 b) {
 }
 
 // LU with partial pivoting of the tridiagonal H (diag alpha, super beta,
-// sub delta), one thread.  Row i of U is (1/U0i[i])^{-1}, U1[i], U2[i] on
-// columns i, i+1, i+2; Lm[i] is the multiplier eliminating column i of the
-// row below the pivot row; Sw[i] says whether rows i and i+1 were exchanged.
-__global__ void k_tri_lu(int k, const C64* __restrict__ alpha, const C64* __restrict__ beta,
-                         const C64* __restrict__ delta, C64* __restrict__ Lm, int* __restrict__ Sw,
-                         C64* __restrict__ U0i, C64* __restrict__ U1, C64* __restrict__ U2, int* __restrict__ sing) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// sub delta).  Row i of U holds 1/U0i[i], U1[i], U2[i] on columns i, i+1, i+2;
+// Lm[i] is the multiplier that eliminates column i of the row below the
+// pivot row; Sw[i] says whether rows i and i+1 were exchanged.  The
+// elimination is sequential (one thread); the coefficients are first staged
+// in LDS by the whole block so the loop does not wait on global memory.
+constexpr int TRI_LDS_MAX = 1365;  // 3 k complex in LDS (<= 64 KB of dynamic LDS)
+
+__global__ void __launch_bounds__(256) k_tri_lu(int k, const C64* __restrict__ alpha, const C64* __restrict__ beta,
+                                                const C64* __restrict__ delta, C64* __restrict__ Lm,
+                                                int* __restrict__ Sw, C64* __restrict__ U0i, C64* __restrict__ U1,
+                                                C64* __restrict__ U2, int* __restrict__ sing) {
+  extern __shared__ C64 sm[];
+  const bool lds = k <= TRI_LDS_MAX;
+  if (lds) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+      sm[i] = alpha[i];
+      sm[k + i] = i + 1 < k ? beta[i] : mk(0.0, 0.0);
+      sm[2 * k + i] = i + 1 < k ? delta[i] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const C64* al = lds ? sm : alpha;
+  const C64* be = lds ? sm + k : beta;
+  const C64* de = lds ? sm + 2 * k : delta;
   const C64 z = mk(0.0, 0.0);
-  C64 a0 = alpha[0], a1 = k > 1 ? beta[0] : z, a2 = z;
+  C64 a0 = al[0], a1 = k > 1 ? be[0] : z, a2 = z;
   int bad = 0;
   for (int i = 0; i + 1 < k; ++i) {
-    const C64 b0 = delta[i], b1 = alpha[i + 1], b2 = (i + 2 < k) ? beta[i + 1] : z;
-    C64 p0, p1, p2, o0, o1, o2;
-    int sw;
-    if (cabs1s(a0) >= cabs1s(b0)) {
-      p0 = a0; p1 = a1; p2 = a2; o0 = b0; o1 = b1; o2 = b2; sw = 0;
-    } else {
-      p0 = b0; p1 = b1; p2 = b2; o0 = a0; o1 = a1; o2 = a2; sw = 1;
-    }
+    const C64 b0 = de[i], b1 = al[i + 1], b2 = (i + 2 < k) ? be[i + 1] : z;
+    const bool sw = cabs1s(a0) < cabs1s(b0);
+    const C64 p0 = sw ? b0 : a0, p1 = sw ? b1 : a1, p2 = sw ? b2 : a2;
+    const C64 o0 = sw ? a0 : b0, o1 = sw ? a1 : b1, o2 = sw ? a2 : b2;
     if (!(cabs1s(p0) > 0.0)) bad = 1;
-    const C64 m = cdiv(o0, p0);
-    U0i[i] = cdiv(mk(1.0, 0.0), p0);
+    const C64 inv = cdiv(mk(1.0, 0.0), p0);
+    const C64 m = cmul(o0, inv);
+    U0i[i] = inv;
     U1[i] = p1;
     U2[i] = p2;
     Lm[i] = m;
-    Sw[i] = sw;
+    Sw[i] = sw ? 1 : 0;
     a0 = o1 - cmul(m, p1);
     a1 = o2 - cmul(m, p2);
     a2 = z;
@@ -68,28 +83,49 @@ __global__ void k_tri_lu(int k, const C64* __restrict__ alpha, const C64* __rest
   *sing = bad;
 }
 
-// column j of H^{-1} (solve H x = e_j), then B = H + H^{-1}; B row-major k x k
+// column j of H^{-1} (solve H x = e_j), then B = H + H^{-1}; B row-major k x k.
+// The factors are staged in LDS when they fit.  The forward sweep of e_j is
+// zero before row j - 1, so it starts there.
+struct TriF {
+  C64 lm, u0i, u1, u2;
+};
+constexpr int TRI_INV_LDS_MAX = 1024;  // k x 64 B in LDS (<= 64 KB of dynamic LDS)
+
 __global__ void __launch_bounds__(64) k_tri_inv(int k, const C64* __restrict__ Lm, const int* __restrict__ Sw,
                                                 const C64* __restrict__ U0i, const C64* __restrict__ U1,
                                                 const C64* __restrict__ U2, const C64* __restrict__ alpha,
                                                 const C64* __restrict__ beta, const C64* __restrict__ delta,
                                                 C64* __restrict__ B) {
+  extern __shared__ TriF sf[];
+  const bool lds = k <= TRI_INV_LDS_MAX;
+  if (lds) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+      sf[i].lm = Lm[i];
+      sf[i].u0i = U0i[i];
+      sf[i].u1 = U1[i];
+      sf[i].u2 = U2[i];
+    }
+    __syncthreads();
+  }
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k) return;
   const C64 z = mk(0.0, 0.0);
+  const int i0 = j > 0 ? j - 1 : 0;
+  for (int i = 0; i < i0; ++i) B[(size_t)i * k + j] = z;
   C64 fc = (j == 0) ? mk(1.0, 0.0) : z;
-  for (int i = 0; i + 1 < k; ++i) {
+  for (int i = i0; i + 1 < k; ++i) {
     const C64 fn = (i + 1 == j) ? mk(1.0, 0.0) : z;
     const int sw = Sw[i];
     const C64 piv = sw ? fn : fc, oth = sw ? fc : fn;
     B[(size_t)i * k + j] = piv;
-    fc = oth - cmul(Lm[i], piv);
+    fc = oth - cmul(lds ? sf[i].lm : Lm[i], piv);
   }
   B[(size_t)(k - 1) * k + j] = fc;
   C64 x1 = z, x2 = z;
   for (int i = k - 1; i >= 0; --i) {
     const C64 y = B[(size_t)i * k + j];
-    const C64 xi = cmul(y - cmul(U1[i], x1) - cmul(U2[i], x2), U0i[i]);
+    const C64 u1 = lds ? sf[i].u1 : U1[i], u2 = lds ? sf[i].u2 : U2[i], u0 = lds ? sf[i].u0i : U0i[i];
+    const C64 xi = cmul(y - cmul(u1, x1) - cmul(u2, x2), u0);
     B[(size_t)i * k + j] = xi;
     x2 = x1;
     x1 = xi;
@@ -129,29 +165,41 @@ __global__ void k_tri_dense(int k, const C64* __restrict__ alpha, const C64* __r
 }
 
 // ---------------------------------------------------------------------------
-// inner Krylov on dense B.  V, W column-major (column j at j*k); u, q the
-// work vectors; coefficients a[l], b[l] (super), d[l] (sub); flags[0] =
-// breakdown step.
+// inner Krylov on dense B: three launches per step.
+//  k_in_gemv : normalise the previous raw vectors (from partial sums), store
+//              v_i / w_i, u = B v_i - beta v_{i-1}, q = B^dag w_i - delta w_{i-1}
+//              (one wave per row), and the partial first-pass projections
+//              W^dag u, V^dag q over the block's four rows;
+//  k_in_sub  : reduce the partial projections, subtract (u -= V c, q -= W d;
+//              eight lanes per row), then emit either the partial projections
+//              of the second Gram-Schmidt pass or the partial sums of
+//              s = q^dag u, |u|^2, |q|^2 for the next normalisation.
+// V, W column-major (column j at j*k).  Hermitian: one side, W = V, q = u.
+constexpr int GR = 16;  // rows per k_in_gemv block (one wave each, 1024 threads)
+constexpr int LMAX = 512;  // largest inner size (LDS of k_in_sub)
+constexpr int SR = 32;  // rows per k_in_sub block (eight lanes each)
+
 struct Inner {
-  int k, herm;
+  int k, herm, lmax;
   const C64* B;
   const C64* BH;
   C64* V;
   C64* W;
   C64* uraw[2];  // ping-pong raw vectors (u side)
   C64* qraw[2];  // (q side)
-  C64* cproj;    // [l] projections W^dag u
-  C64* dproj;    // [l] projections V^dag q
+  C64* part1;    // [2][nb1][lmax] partial projections from k_in_gemv
+  C64* part2;    // [2][nb2][lmax] second-pass partial projections
+  double* part3; // [4][nb2] normalisation partial sums
+  int nb1, nb2;
   C64* a;
   C64* b;
   C64* d;
-  double* part;  // [4][nb3]
-  int nb3;
   int* flags;
 };
 
+template <int NTH>
 __device__ __forceinline__ void bsum(double (&v)[4]) {
-  __shared__ double sh[4][ST / 64];
+  __shared__ double sh[4][NTH / 64];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -162,125 +210,191 @@ __device__ __forceinline__ void bsum(double (&v)[4]) {
     for (int q = 0; q < 4; ++q) sh[q][threadIdx.x >> 6] = v[q];
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+  for (int q = 0; q < 4; ++q) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NTH / 64; ++w) t += sh[q][w];
+    v[q] = t;
+  }
 }
 
-// IK1: finish step i-1 (normalise), then u = B v_i - beta_{i-1} v_{i-1},
-// q = B^dag w_i - delta_{i-1} w_{i-1}.  One wave per row; blockIdx.y = side.
-__global__ void __launch_bounds__(ST) k_in_gemv(Inner s, int i) {
+__global__ void __launch_bounds__(GR * 64) k_in_gemv(Inner s, int i) {
   if (s.flags[0]) return;
   const int k = s.k;
   const int side = blockIdx.y;  // 0: u = B v, 1: q = B^dag w
-  const C64* src_u = s.uraw[i & 1];
-  const C64* src_q = s.qraw[i & 1];
+  const C64* src = side ? s.qraw[i & 1] : s.uraw[i & 1];
   C64* dst = side ? s.qraw[(i + 1) & 1] : s.uraw[(i + 1) & 1];
-  double sv = 1.0;
-  C64 sw = mk(1.0, 0.0), beta = mk(0.0, 0.0);
-  double delta = 0.0;
+  C64 scal = mk(1.0, 0.0), sub = mk(0.0, 0.0);
+  C64 scal_o = mk(1.0, 0.0);  // scale of the other side's new column
   if (i > 0) {
     double v[4] = {0, 0, 0, 0};
-    for (int bb = threadIdx.x; bb < s.nb3; bb += ST)
+    for (int bb = threadIdx.x; bb < s.nb2; bb += GR * 64)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] += s.part[q * s.nb3 + bb];
-    bsum(v);
-    C64 sd = mk(v[0], v[1]);
-    if (s.herm) sd = mk(v[2], 0.0);
+      for (int q = 0; q < 4; ++q) v[q] += s.part3[q * s.nb2 + bb];
+    bsum<GR * 64>(v);
+    const C64 sd = s.herm ? mk(v[2], 0.0) : mk(v[0], v[1]);
     const double sabs = sqrt(norm2(sd));
     if (!(sabs > 1e-14 * sqrt(v[2] * (s.herm ? v[2] : v[3])))) {
       if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) s.flags[0] = i;
       return;
     }
-    delta = sqrt(sabs);
-    beta = (1.0 / delta) * sd;
-    sv = 1.0 / delta;
-    sw = (1.0 / norm2(beta)) * beta;
+    const double delta = sqrt(sabs);
+    const C64 beta = (1.0 / delta) * sd;
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
       s.b[i - 1] = beta;
       s.d[i - 1] = mk(delta, 0.0);
     }
+    const C64 sv = mk(1.0 / delta, 0.0), sw = (1.0 / norm2(beta)) * beta;  // v = u / delta, w = q / conj(beta)
+    scal = side ? sw : sv;
+    scal_o = side ? sv : sw;
+    sub = side ? mk(delta, 0.0) : beta;
   }
+  __shared__ C64 s_x[GR];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = blockIdx.x * (ST / 64) + wave;
-  if (r >= k) return;
+  const int r = blockIdx.x * GR + wave;
   const C64* M = side ? s.BH : s.B;
-  // this wave also stores the normalised row r of v_i / w_i
-  const C64* xs = side ? src_q : src_u;
-  const C64 scal = side ? sw : mk(sv, 0.0);
-  C64 acc = mk(0.0, 0.0);
-  for (int c = lane; c < k; c += 64) {
-    const C64 xv = (i > 0) ? cmul(scal, xs[c]) : mk(c == 0 ? 1.0 : 0.0, 0.0);
-    acc = acc + cmul(M[(size_t)r * k + c], xv);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    acc.re += __shfl_xor(acc.re, o, 64);
-    acc.im += __shfl_xor(acc.im, o, 64);
-  }
-  if (lane == 0) {
-    C64* col = (side ? s.W : s.V) + (size_t)i * k;
-    const C64 xr = (i > 0) ? cmul(scal, xs[r]) : mk(r == 0 ? 1.0 : 0.0, 0.0);
-    col[r] = xr;
-    if (i > 0) {
-      const C64* prev = (side ? s.W : s.V) + (size_t)(i - 1) * k;
-      acc = acc - cmul(side ? mk(delta, 0.0) : beta, prev[r]);
+  C64* basis = side ? s.W : s.V;
+  if (r < k) {
+    C64 acc = mk(0.0, 0.0);
+    for (int c = lane; c < k; c += 64) {
+      const C64 xv = (i > 0) ? cmul(scal, src[c]) : mk(c == 0 ? 1.0 : 0.0, 0.0);
+      acc = acc + cmul(M[(size_t)r * k + c], xv);
     }
-    dst[r] = acc;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      acc.re += __shfl_xor(acc.re, o, 64);
+      acc.im += __shfl_xor(acc.im, o, 64);
+    }
+    if (lane == 0) {
+      const C64 xr = (i > 0) ? cmul(scal, src[r]) : mk(r == 0 ? 1.0 : 0.0, 0.0);
+      basis[(size_t)i * k + r] = xr;
+      if (i > 0) acc = acc - cmul(sub, basis[(size_t)(i - 1) * k + r]);
+      dst[r] = acc;
+      s_x[wave] = acc;
+    }
+  } else if (lane == 0) {
+    s_x[wave] = mk(0.0, 0.0);
+  }
+  __syncthreads();
+  // partial first-pass projections over this block's rows.  Column i of the
+  // other basis is being written by the other side's blocks in this same
+  // launch, so its entries are recomputed here from the raw vector.
+  const bool other = !s.herm;
+  const C64* proj = s.herm ? s.V : (side ? s.V : s.W);
+  const C64* osrc = side ? s.uraw[i & 1] : s.qraw[i & 1];
+  C64* out = s.part1 + ((size_t)side * s.nb1 + blockIdx.x) * s.lmax;
+  for (int j = threadIdx.x; j <= i; j += GR * 64) {
+    C64 t = mk(0.0, 0.0);
+#pragma unroll
+    for (int w = 0; w < GR; ++w) {
+      const int rr = blockIdx.x * GR + w;
+      if (rr < k) {
+        C64 pv;
+        if (j == i && other) pv = (i > 0) ? cmul(scal_o, osrc[rr]) : mk(rr == 0 ? 1.0 : 0.0, 0.0);
+        else pv = proj[(size_t)j * k + rr];
+        t = t + cmulc(pv, s_x[w]);
+      }
+    }
+    out[j] = t;
   }
 }
 
-// IK2: projections c_j = w_j^dag u and d_j = v_j^dag q for j <= i (blockIdx.y = side)
-__global__ void __launch_bounds__(ST) k_in_proj(Inner s, int i, int first) {
-  if (s.flags[0]) return;
-  const int j = blockIdx.x, side = blockIdx.y, k = s.k;
-  const C64* basis = s.herm ? s.V + (size_t)j * k : (side ? s.V : s.W) + (size_t)j * k;
-  const C64* x = side ? s.qraw[(i + 1) & 1] : s.uraw[(i + 1) & 1];
-  double v[4] = {0, 0, 0, 0};
-  for (int r = threadIdx.x; r < k; r += ST) {
-    const C64 t = cmulc(basis[r], x[r]);
-    v[0] += t.re;
-    v[1] += t.im;
-  }
-  bsum(v);
-  if (threadIdx.x == 0) {
-    const C64 c = mk(v[0], v[1]);
-    (side ? s.dproj : s.cproj)[j] = c;
-    if (first && side == 0 && j == i) s.a[i] = s.herm ? mk(c.re, 0.0) : c;
-  }
-}
-
-// IK3: u -= V c, q -= W d for the rows of this block; with `last`, partial
-// sums of s = q^dag u, |u|^2, |q|^2 for the next normalisation
+// pass 1 (last == 0): reduce part1, subtract, emit part2;
+// pass 2 (last == 1): reduce part2, subtract, emit the normalisation sums
 __global__ void __launch_bounds__(ST) k_in_sub(Inner s, int i, int last) {
   if (s.flags[0]) return;
   const int k = s.k;
-  const int r = blockIdx.x * ST + threadIdx.x;
+  const int sides = s.herm ? 1 : 2;
+  __shared__ C64 s_c[2][LMAX];
+  __shared__ C64 s_u[2][SR];
+  const C64* pin = last ? s.part2 : s.part1;
+  const int nbin = last ? s.nb2 : s.nb1;
+  for (int side = 0; side < sides; ++side)
+    for (int j = threadIdx.x; j <= i; j += ST) {
+      // four independent partial sums so that the loads overlap (a single
+      // running sum would wait for every load in turn)
+      C64 t0 = mk(0.0, 0.0), t1 = t0, t2 = t0, t3 = t0;
+      const C64* pp = pin + (size_t)side * nbin * s.lmax + j;
+      int bb = 0;
+      for (; bb + 4 <= nbin; bb += 4) {
+        t0 = t0 + pp[(size_t)(bb + 0) * s.lmax];
+        t1 = t1 + pp[(size_t)(bb + 1) * s.lmax];
+        t2 = t2 + pp[(size_t)(bb + 2) * s.lmax];
+        t3 = t3 + pp[(size_t)(bb + 3) * s.lmax];
+      }
+      for (; bb < nbin; ++bb) t0 = t0 + pp[(size_t)bb * s.lmax];
+      const C64 t = (t0 + t1) + (t2 + t3);
+      s_c[side][j] = t;
+      if (!last && side == 0 && j == i && blockIdx.x == 0) s.a[i] = s.herm ? mk(t.re, 0.0) : t;
+    }
+  __syncthreads();
+  // u -= V c, q -= W d: eight lanes per row
+  const int rl = threadIdx.x >> 3, jl = threadIdx.x & 7;
+  const int r = blockIdx.x * SR + rl;
   C64* u = s.uraw[(i + 1) & 1];
   C64* q = s.qraw[(i + 1) & 1];
+  for (int side = 0; side < sides; ++side) {
+    const C64* basis = side ? s.W : s.V;
+    C64 acc = mk(0.0, 0.0), acc1 = acc;
+    if (r < k) {
+      int j = jl;
+      for (; j + 8 <= i; j += 16) {
+        acc = acc + cmul(basis[(size_t)j * k + r], s_c[side][j]);
+        acc1 = acc1 + cmul(basis[(size_t)(j + 8) * k + r], s_c[side][j + 8]);
+      }
+      for (; j <= i; j += 8) acc = acc + cmul(basis[(size_t)j * k + r], s_c[side][j]);
+    }
+    acc = acc + acc1;
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) {
+      acc.re += __shfl_xor(acc.re, o, 64);
+      acc.im += __shfl_xor(acc.im, o, 64);
+    }
+    if (jl == 0) {
+      C64 nv = mk(0.0, 0.0);
+      if (r < k) {
+        C64* x = side ? q : u;
+        nv = x[r] - acc;
+        x[r] = nv;
+      }
+      s_u[side][rl] = nv;
+    }
+  }
+  __syncthreads();
+  if (!last) {
+    // second-pass partial projections over this block's rows
+    for (int side = 0; side < sides; ++side) {
+      const C64* proj = s.herm ? s.V : (side ? s.V : s.W);
+      C64* out = s.part2 + ((size_t)side * s.nb2 + blockIdx.x) * s.lmax;
+      const int nr = min(SR, k - blockIdx.x * SR);  // rows of this block (s_u is zero past them)
+      for (int j = threadIdx.x; j <= i; j += ST) {
+        const C64* pj = proj + (size_t)j * k + blockIdx.x * SR;
+        C64 t0 = mk(0.0, 0.0), t1 = t0;
+        int w = 0;
+        for (; w + 2 <= nr; w += 2) {
+          t0 = t0 + cmulc(pj[w], s_u[side][w]);
+          t1 = t1 + cmulc(pj[w + 1], s_u[side][w + 1]);
+        }
+        if (w < nr) t0 = t0 + cmulc(pj[w], s_u[side][w]);
+        out[j] = t0 + t1;
+      }
+    }
+    return;
+  }
   double v[4] = {0, 0, 0, 0};
-  if (r < k) {
-    C64 du = mk(0.0, 0.0), dq = mk(0.0, 0.0);
-    for (int j = 0; j <= i; ++j) {
-      du = du + cmul(s.V[(size_t)j * k + r], s.cproj[j]);
-      if (!s.herm) dq = dq + cmul(s.W[(size_t)j * k + r], s.dproj[j]);
-    }
-    const C64 un = u[r] - du;
-    u[r] = un;
-    C64 qn = un;
-    if (!s.herm) {
-      qn = q[r] - dq;
-      q[r] = qn;
-    }
+  if (threadIdx.x < SR) {
+    const C64 un = s_u[0][threadIdx.x];
+    const C64 qn = s.herm ? un : s_u[1][threadIdx.x];
     const C64 t = cmulc(qn, un);
     v[0] = t.re;
     v[1] = t.im;
     v[2] = norm2(un);
     v[3] = norm2(qn);
   }
-  if (!last) return;
-  bsum(v);
+  bsum<ST>(v);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) s.part[qq * s.nb3 + blockIdx.x] = v[qq];
+    for (int qq = 0; qq < 4; ++qq) s.part3[qq * s.nb2 + blockIdx.x] = v[qq];
 }
 
 // z = V y (k rows, l columns)
@@ -329,7 +443,11 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     return e;
   }
   // nested
-  const int nb3 = (k + ST - 1) / ST;
+  if (ell > LMAX) {
+    set_error("inner Krylov size %d exceeds %d", ell, LMAX);
+    return NK_EINVAL;
+  }
+  const int nb1 = (k + GR - 1) / GR, nb2 = (k + SR - 1) / SR;
   const size_t kk = (size_t)k * k;
   size_t bytes = 0;
   auto take = [&](size_t b) {
@@ -343,8 +461,10 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
   const size_t oW = take(hermitian ? 0 : (size_t)k * ell * sizeof(C64));
   const size_t oR = take((size_t)4 * k * sizeof(C64));
   const size_t oF = take((size_t)5 * k * sizeof(C64) + (size_t)k * sizeof(int));
-  const size_t oC = take((size_t)5 * ell * sizeof(C64));
-  const size_t oP = take((size_t)4 * nb3 * sizeof(double));
+  const size_t oC = take((size_t)3 * ell * sizeof(C64));
+  const size_t oP1 = take((size_t)2 * nb1 * ell * sizeof(C64));
+  const size_t oP2 = take((size_t)2 * nb2 * ell * sizeof(C64));
+  const size_t oP3 = take((size_t)4 * nb2 * sizeof(double));
   const size_t oS = take((size_t)ell * ell * sizeof(C64));
   const size_t oI = take(8 * sizeof(int));
   if (g_small.ensure(bytes)) return NK_ENOMEM;
@@ -352,6 +472,7 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
   Inner s;
   s.k = k;
   s.herm = hermitian;
+  s.lmax = ell;
   s.B = (C64*)(base + oB);
   s.BH = hermitian ? s.B : (C64*)(base + oBH);
   s.V = (C64*)(base + oV);
@@ -365,34 +486,34 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
   C64 *Lm = F, *U0i = F + k, *U1 = F + 2 * k, *U2 = F + 3 * k;
   int* Sw = (int*)(F + 5 * k);
   C64* Cc = (C64*)(base + oC);
-  s.cproj = Cc;
-  s.dproj = Cc + ell;
-  s.a = Cc + 2 * ell;
-  s.b = Cc + 3 * ell;
-  s.d = Cc + 4 * ell;
-  s.part = (double*)(base + oP);
-  s.nb3 = nb3;
+  s.a = Cc;
+  s.b = Cc + ell;
+  s.d = Cc + 2 * ell;
+  s.part1 = (C64*)(base + oP1);
+  s.part2 = (C64*)(base + oP2);
+  s.part3 = (double*)(base + oP3);
+  s.nb1 = nb1;
+  s.nb2 = nb2;
   C64* Hl = (C64*)(base + oS);
   int* iflags = (int*)(base + oI);
   s.flags = iflags;
   NK_HIP(hipMemsetAsync(iflags, 0, 8 * sizeof(int), st));
   NK_HIP(hipMemsetAsync(s.b, 0, 2 * ell * sizeof(C64), st));
 
-  hipLaunchKernelGGL(k_tri_lu, dim3(1), dim3(64), 0, st, k, alpha, beta, delta, Lm, Sw, U0i, U1, U2, iflags + 1);
-  hipLaunchKernelGGL(k_tri_inv, dim3((k + 63) / 64), dim3(64), 0, st, k, Lm, Sw, U0i, U1, U2, alpha, beta, delta,
-                     (C64*)s.B);
+  const size_t lds_lu = k <= TRI_LDS_MAX ? (size_t)3 * k * sizeof(C64) : 0;
+  const size_t lds_inv = k <= TRI_INV_LDS_MAX ? (size_t)k * sizeof(TriF) : 0;
+  hipLaunchKernelGGL(k_tri_lu, dim3(1), dim3(256), lds_lu, st, k, alpha, beta, delta, Lm, Sw, U0i, U1, U2,
+                     iflags + 1);
+  hipLaunchKernelGGL(k_tri_inv, dim3((k + 63) / 64), dim3(64), lds_inv, st, k, Lm, Sw, U0i, U1, U2, alpha, beta,
+                     delta, (C64*)s.B);
   if (!hermitian) hipLaunchKernelGGL(k_adjoint, dim3((k + 31) / 32, (k + 31) / 32), dim3(32, 8), 0, st, k, s.B,
                                      (C64*)s.BH);
   NK_HIP(hipGetLastError());
   const int sides = hermitian ? 1 : 2;
   for (int i = 0; i < ell; ++i) {
-    hipLaunchKernelGGL(k_in_gemv, dim3((k + 3) / 4, sides), dim3(ST), 0, st, s, i);
-    hipLaunchKernelGGL(k_in_proj, dim3(i + 1, sides), dim3(ST), 0, st, s, i, 1);
-    if (i + 1 < ell) {
-      hipLaunchKernelGGL(k_in_sub, dim3(nb3), dim3(ST), 0, st, s, i, 0);
-      hipLaunchKernelGGL(k_in_proj, dim3(i + 1, sides), dim3(ST), 0, st, s, i, 0);
-      hipLaunchKernelGGL(k_in_sub, dim3(nb3), dim3(ST), 0, st, s, i, 1);
-    }
+    hipLaunchKernelGGL(k_in_gemv, dim3(nb1, sides), dim3(GR * 64), 0, st, s, i);
+    hipLaunchKernelGGL(k_in_sub, dim3(nb2), dim3(ST), 0, st, s, i, 0);
+    if (i + 1 < ell) hipLaunchKernelGGL(k_in_sub, dim3(nb2), dim3(ST), 0, st, s, i, 1);
   }
   NK_HIP(hipGetLastError());
   int fl[2] = {0, 0};

@@ -130,23 +130,78 @@ __device__ __forceinline__ void pin(Cx<R> (&acc)[NF][12]) {
     for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(acc[f][c].re), "+v"(acc[f][c].im));
 }
 
-// one direction nu, both hops, for NF fields at once (one link load serves all)
-template <int NU, class R, int NF, class LK>
-__device__ __forceinline__ void hop_dir(const Geom& g, int s, int coord, const LK& lk,
-                                        const Cx<R>* const (&in)[NF], const R (&cf)[NF], const R (&cb)[NF],
-                                        Cx<R> (&acc)[NF][12]) {
-  using P = Proj<NU>;
-  const int L = g.L[NU], st = g.stride[NU], V = g.V;
-  const int sf = (coord == L - 1) ? s - (L - 1) * st : s + st;
-  const int sb = (coord == 0) ? s + (L - 1) * st : s - st;
-  const R bf = (NU == 3 && coord == L - 1) ? R(-1) : R(1);
-  const R bb = (NU == 3 && coord == 0) ? R(-1) : R(1);
-  Cx<R> u[9];
-  // Each hop is scheduled on its own: letting the scheduler hoist the loads
-  // of all eight hops at once needs more than 512 registers per lane and
-  // spills to scratch.  One hop keeps 9 + 12 NF complex loads in flight.
+// coordinates of a device site: local (within the tile) and tile coordinates
+struct SiteC {
+  int cl[4], ct[4];
+};
+
+__device__ __forceinline__ SiteC site_coords(const Geom& g, int s) {
+  SiteC c;
+  int l = s & ((1 << g.lts) - 1);
+  int T = s >> g.lts;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    c.cl[d] = l & (g.b[d] - 1);
+    l >>= g.lb[d];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c.ct[d] = T % g.nt[d];
+    T /= g.nt[d];
+  }
+  c.ct[3] = T;
+  return c;
+}
+
+// neighbour x + nu and x - nu; *wrap is set when the hop crosses the
+// lattice boundary in direction nu
+template <int NU>
+__device__ __forceinline__ int nbr_fwd(const Geom& g, int s, const SiteC& c, bool* wrap) {
+  *wrap = false;
+  if (c.cl[NU] < g.b[NU] - 1) return s + g.lstr[NU];
+  const int base = s - (g.b[NU] - 1) * g.lstr[NU];
+  if (c.ct[NU] == g.nt[NU] - 1) {
+    *wrap = true;
+    return base - (g.nt[NU] - 1) * g.tstr[NU];
+  }
+  return base + g.tstr[NU];
+}
+template <int NU>
+__device__ __forceinline__ int nbr_bwd(const Geom& g, int s, const SiteC& c, bool* wrap) {
+  *wrap = false;
+  if (c.cl[NU] > 0) return s - g.lstr[NU];
+  const int base = s + (g.b[NU] - 1) * g.lstr[NU];
+  if (c.ct[NU] == 0) {
+    *wrap = true;
+    return base + (g.nt[NU] - 1) * g.tstr[NU];
+  }
+  return base - g.tstr[NU];
+}
+
+#ifndef NK_HOP_FENCE
+#define NK_HOP_FENCE 1  // schedule each hop on its own (bounded registers)
+#endif
+#ifndef NK_HOP_ORDER
+#define NK_HOP_ORDER 0  // 0: x, y, z, t (forward then backward per direction); 1: all forward hops, then all backward
+#endif
+
+__device__ __forceinline__ void hop_fence() {
+#if NK_HOP_FENCE
   __builtin_amdgcn_sched_barrier(0);
-  // forward hop: (1 - gamma) U_nu(x) psi(x + nu)
+#endif
+}
+
+// forward hop in direction nu for NF fields: (1 - gamma) U_nu(x) psi(x + nu)
+template <int NU, class R, int NF, class LK>
+__device__ __forceinline__ void hop_fwd(const Geom& g, int s, const SiteC& sc0, const LK& lk,
+                                        const Cx<R>* const (&in)[NF], const R (&cf)[NF], Cx<R> (&acc)[NF][12]) {
+  using P = Proj<NU>;
+  const int V = g.V;
+  bool wrap;
+  const int sf = nbr_fwd<NU>(g, s, sc0, &wrap);
+  const R bf = (NU == 3 && wrap) ? R(-1) : R(1);
+  Cx<R> u[9];
+  hop_fence();
   lk.load(NU, s, u);
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
@@ -170,8 +225,19 @@ __device__ __forceinline__ void hop_dir(const Geom& g, int s, int coord, const L
     }
   }
   pin<R, NF>(acc);
-  __builtin_amdgcn_sched_barrier(0);
-  // backward hop: (1 + gamma) U_nu(x - nu)^dag psi(x - nu)
+}
+
+// backward hop in direction nu for NF fields: (1 + gamma) U_nu(x - nu)^dag psi(x - nu)
+template <int NU, class R, int NF, class LK>
+__device__ __forceinline__ void hop_bwd(const Geom& g, int s, const SiteC& sc0, const LK& lk,
+                                        const Cx<R>* const (&in)[NF], const R (&cb)[NF], Cx<R> (&acc)[NF][12]) {
+  using P = Proj<NU>;
+  const int V = g.V;
+  bool wrap;
+  const int sb = nbr_bwd<NU>(g, s, sc0, &wrap);
+  const R bb = (NU == 3 && wrap) ? R(-1) : R(1);
+  Cx<R> u[9];
+  hop_fence();
   lk.load(NU, sb, u);
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
@@ -202,13 +268,10 @@ __device__ __forceinline__ void hop_dir(const Geom& g, int s, int coord, const L
 template <class R, int NF, class LK>
 __device__ __forceinline__ void hopping(const Geom& g, int s, const LK& lk, const Cx<R>* const (&in)[NF],
                                         const R (&eft)[NF], const R (&ebt)[NF], Cx<R> (&acc)[NF][12]) {
-  int r = s;
-  const int x = r % g.L[0];
-  r /= g.L[0];
-  const int y = r % g.L[1];
-  r /= g.L[1];
-  const int z = r % g.L[2];
-  const int t = r / g.L[2];
+  const SiteC x = site_coords(g, s);
+  const SiteC& y = x;
+  const SiteC& z = x;
+  const SiteC& t = x;
   R one[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
@@ -216,10 +279,25 @@ __device__ __forceinline__ void hopping(const Geom& g, int s, const LK& lk, cons
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[f][c] = mk<R>(0, 0);
   }
-  hop_dir<0>(g, s, x, lk, in, one, one, acc);
-  hop_dir<1>(g, s, y, lk, in, one, one, acc);
-  hop_dir<2>(g, s, z, lk, in, one, one, acc);
-  hop_dir<3>(g, s, t, lk, in, eft, ebt, acc);
+#if NK_HOP_ORDER == 0
+  hop_fwd<0>(g, s, x, lk, in, one, acc);
+  hop_bwd<0>(g, s, x, lk, in, one, acc);
+  hop_fwd<1>(g, s, y, lk, in, one, acc);
+  hop_bwd<1>(g, s, y, lk, in, one, acc);
+  hop_fwd<2>(g, s, z, lk, in, one, acc);
+  hop_bwd<2>(g, s, z, lk, in, one, acc);
+  hop_fwd<3>(g, s, t, lk, in, eft, acc);
+  hop_bwd<3>(g, s, t, lk, in, ebt, acc);
+#else
+  hop_fwd<0>(g, s, x, lk, in, one, acc);
+  hop_fwd<1>(g, s, y, lk, in, one, acc);
+  hop_fwd<2>(g, s, z, lk, in, one, acc);
+  hop_fwd<3>(g, s, t, lk, in, eft, acc);
+  hop_bwd<0>(g, s, x, lk, in, one, acc);
+  hop_bwd<1>(g, s, y, lk, in, one, acc);
+  hop_bwd<2>(g, s, z, lk, in, one, acc);
+  hop_bwd<3>(g, s, t, lk, in, ebt, acc);
+#endif
 }
 
 // gamma5 sign of component c = spin*3 + colour
@@ -227,9 +305,12 @@ __device__ __forceinline__ constexpr int g5sign(int c) { return c < 6 ? 1 : -1; 
 
 // XCD-aware block order: consecutive logical tiles stay on one XCD (the
 // hardware hands workgroup b to XCD b % 8), so neighbouring sites share an L2.
+#ifndef NK_XCD_MAP
+#define NK_XCD_MAP 1
+#endif
 __device__ __forceinline__ int xcd_block() {
   const int nb = gridDim.x, b = blockIdx.x;
-  if ((nb & 7) != 0) return b;
+  if (!NK_XCD_MAP || (nb & 7) != 0) return b;
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
