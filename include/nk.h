@@ -85,7 +85,9 @@ typedef struct nk_sign_params {
   int32_t rh_maxit;    /* Roberts-Higham iteration cap */
   double rh_tol;       /* Roberts-Higham stop: |S_{n+1} - S_n|_F <= rh_tol |S_{n+1}|_F */
   const int32_t* ell_per_rhs; /* optional host array [nrhs] of per-source ell (NULL = ell for all) */
-  int32_t profile;     /* 1: time every outer-recurrence kernel with HIP events on the caller's stream */
+  int32_t profile;     /* n > 0: time the two outer-recurrence kernels of every n-th step with HIP
+                        * events bound to those launches on the caller's stream (0 = off;
+                        * negative = NK_EINVAL) */
   int32_t reserved;
 } nk_sign_params;
 

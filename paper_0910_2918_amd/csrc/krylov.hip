@@ -20,13 +20,6 @@ namespace nk {
 
 constexpr int NT = 256;
 
-#ifndef NK_SPLIT_PAIR
-#define NK_SPLIT_PAIR 1  // 0: one lane per site (both fields); 1: two lanes per site (one per field)
-#endif
-#ifndef NK_FIELD_MAJOR
-#define NK_FIELD_MAJOR 0  // with NK_SPLIT_PAIR: the first half of the grid applies A to v, the second A^dag to w
-#endif
-
 template <int NQ>
 __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
   __shared__ double sh[NQ][NT / 64];
@@ -44,13 +37,30 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
   for (int q = 0; q < NQ; ++q) v[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
 }
 
+// sum of nb partial sums per quantity, the same value in every thread; the
+// loads go out eight at a time so that long partial arrays cost one or two
+// L2 round trips, not one per element
 template <int NQ>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, double (&v)[NQ]) {
+  constexpr int B = 8;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += NT)
+  for (int b0 = threadIdx.x; b0 < nb; b0 += B * NT) {
+    double t[NQ][B];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] += part[q * nb + b];
+    for (int u = 0; u < B; ++u) {
+      const int b = b0 + u * NT;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) t[q][u] = b < nb ? part[q * nb + b] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double a = 0.0;
+#pragma unroll
+      for (int u = 0; u < B; ++u) a += t[q][u];
+      v[q] += a;
+    }
+  }
   block_sum<NQ>(v);
 }
 
@@ -91,15 +101,37 @@ __global__ void __launch_bounds__(NT) k_start(int n, const C64* __restrict__ x, 
 }
 
 // ---------------------------------------------------------------------------
-// Hermitian Lanczos, K1: w = A v_j - beta_{j-1} v_{j-1}, partial Re(v_j^dag w)
-template <class R, class LK>
+// Hermitian Lanczos, K1: w = A v_j - beta_{j-1} v_{j-1}, partial Re(v_j^dag w).
+// Directions split over the waves of the workgroup (hop_group), one lane per
+// site, 64 sites per wave.  The previous partial sums are loaded before the
+// stencil and reduced after it, so their latency hides behind the stencil
+// loads.
+template <class R, class LK, int NG>
 __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const Cx<R>* __restrict__ vj,
                                              const Cx<R>* __restrict__ vjm1, Cx<R>* __restrict__ p,
                                              const double* __restrict__ partIn, int nbIn,
                                              double* __restrict__ partOut, Coefs c) {
-  if (c.flags[0]) return;
-  double red[1];
-  reduce_partials<1>(partIn, nbIn, red);
+  constexpr int M = 12 / NG;
+  constexpr int NSB = (NT / 64) / NG;  // site blocks of 64 per workgroup
+  __shared__ XBuf<R, NG> xb;
+  const int flag = c.flags[0];
+  double pr[2];  // this thread's share of the previous partial sums (nbIn <= 2 NT)
+#pragma unroll
+  for (int u = 0; u < 2; ++u) pr[u] = threadIdx.x + u * NT < nbIn ? partIn[threadIdx.x + u * NT] : 0.0;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gi = w % NG, sb = w / NG;
+  const int s = (xcd_block() * NSB + sb) * 64 + lane;
+  const bool live = s < g.V;
+  Cx<R> mine[M];
+  {
+    Cx<R> acc[1][12];
+    hop_group<NG>(g, live ? s : 0, lk, vj, gi, R(1), R(1), acc);  // a lane past the end hops at site 0
+    xput<NG>(xb, w, gi, lane, acc, mine);
+  }
+  if (flag) return;
+  double red[1] = {pr[0] + pr[1]};
+  block_sum<1>(red);  // also completes the exchange
   const double beta = sqrt(red[0]);
   if (!(beta > 0.0) || !(beta < 1e300)) {  // invariant subspace reached (or non-finite input)
     if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[0] = j > 0 ? j : -1;
@@ -115,22 +147,21 @@ __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const
     }
   }
   const double bs = beta * svjm1;
-  const int s = xcd_block() * NT + threadIdx.x;
   double dot = 0.0;
-  if (s < g.V) {
-    Cx<R> acc[1][12];
-    const Cx<R>* in[1] = {vj};
-    const R one[1] = {R(1)};
-    hopping<R, 1>(g, s, lk, in, one, one, acc);
+  if (live) {
+    int se = s;
+    asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
 #pragma unroll
-    for (int cc = 0; cc < 12; ++cc) {
-      const size_t i = (size_t)cc * g.V + s;
+    for (int cl = 0; cl < M; ++cl) {
+      const int cc = gi * M + cl;
+      const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
+      const size_t i = (size_t)cc * g.V + se;
       const Cx<R> psi = vj[i];
-      Cx<R> a = diag * psi - R(0.5) * acc[0][cc];
+      Cx<R> a = diag * psi - R(0.5) * hs;
       if (cc >= 6) a = mk<R>(-a.re, -a.im);
-      C64 w = svj * widen(a);
-      if (j > 0) w = w - bs * widen(vjm1[i]);
-      const Cx<R> wr = narrow<R>(w);
+      C64 wv = svj * widen(a);
+      if (j > 0) wv = wv - bs * widen(vjm1[i]);
+      const Cx<R> wr = narrow<R>(wv);
       p[i] = wr;
       const C64 wd = widen(wr), pd = widen(psi);
       dot += pd.re * wd.re + pd.im * wd.im;
@@ -174,101 +205,47 @@ __global__ void __launch_bounds__(NT) k_lan2(int n, int j, const Cx<R>* __restri
 // partial w_j^dag (A v_j) for alpha_j.  It first finishes the previous step:
 // s -> delta_{j-1} = sqrt|s|, beta_{j-1} = s / delta_{j-1}, and detects a
 // serious breakdown |s| <= 1e-14 |v_hat| |w_hat|.
-template <class R, class LK>
+// Directions split over the waves of the workgroup (hop_group); two lanes per
+// site, the even lane on A v_j, the odd lane on A^dag w_j (both read the same
+// link in the same instruction); 32 sites per wave.  The previous partial
+// sums are loaded before the stencil and reduced after it.
+template <class R, class LK, int NG>
 __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt, int j,
                                              const Cx<R>* __restrict__ vj, const Cx<R>* __restrict__ wj,
                                              const Cx<R>* __restrict__ vjm1, const Cx<R>* __restrict__ wjm1,
                                              Cx<R>* __restrict__ p, Cx<R>* __restrict__ q,
                                              const double* __restrict__ partIn, int nbIn,
                                              double* __restrict__ partOut, Coefs c) {
-  if (c.flags[0]) return;
-  double red[4];
-  reduce_partials<4>(partIn, nbIn, red);
-  const C64 sdot = mk(red[0], red[1]);
-  const double sabs = sqrt(norm2(sdot));
-  if (j == 0 && !(sabs > 0.0 && sabs < 1e300)) {  // zero or non-finite source
-    if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[0] = -1;
-    return;
-  }
-  if (j > 0 && !(sabs > 1e-14 * sqrt(red[2] * red[3]))) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) c.flags[0] = j;
-    return;
-  }
-  const double delta = sqrt(sabs);
-  const C64 beta = (1.0 / delta) * sdot;
-  const double svj = 1.0 / delta;
-  const C64 swj = (1.0 / norm2(beta)) * beta;  // 1 / conj(beta)
-  double svjm1 = 0.0;
-  C64 swjm1 = mk(0.0, 0.0);
-  if (j > 0) {
-    svjm1 = c.sv[j - 1];
-    swjm1 = c.sw[j - 1];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    c.sv[j] = svj;
-    c.sw[j] = swj;
-    if (j > 0) {
-      c.beta[j - 1] = beta;
-      c.delta[j - 1] = mk(delta, 0.0);
-    }
-  }
-  const C64 bv = svjm1 * beta;  // beta_{j-1} sv_{j-1}
-  const C64 dw = delta * swjm1;                                       // delta_{j-1} sw_{j-1}
-  const int s = xcd_block() * NT + threadIdx.x;
-  double dre = 0.0, dim = 0.0;
-  if (s < g.V) {
-    Cx<R> acc[2][12];
-    const Cx<R>* in[2] = {vj, wj};
-    const R ef[2] = {eft, ebt};
-    const R eb[2] = {ebt, eft};
-    hopping<R, 2>(g, s, lk, in, ef, eb, acc);
+  constexpr int M = 12 / NG;
+  constexpr int NSB = (NT / 64) / NG;  // site blocks of 32 per workgroup
+  __shared__ XBuf<R, NG> xb;
+  const int flag = c.flags[0];
+  double pr[4][2];  // this thread's share of the previous partial sums (nbIn <= 2 NT)
 #pragma unroll
-    for (int cc = 0; cc < 12; ++cc) {
-      const size_t i = (size_t)cc * g.V + s;
-      const Cx<R> pv = vj[i], pw = wj[i];
-      Cx<R> av = diag * pv - R(0.5) * acc[0][cc];
-      Cx<R> aw = diag * pw - R(0.5) * acc[1][cc];
-      if (cc >= 6) {
-        av = mk<R>(-av.re, -av.im);
-        aw = mk<R>(-aw.re, -aw.im);
-      }
-      const C64 avd = widen(av);
-      const C64 t = cmulc(widen(pw), avd);
-      dre += t.re;
-      dim += t.im;
-      C64 pp = svj * avd;
-      C64 qq = cmul(swj, widen(aw));
-      if (j > 0) {
-        pp = pp - cmul(bv, widen(vjm1[i]));
-        qq = qq - cmul(dw, widen(wjm1[i]));
-      }
-      p[i] = narrow<R>(pp);
-      q[i] = narrow<R>(qq);
+  for (int qd = 0; qd < 4; ++qd)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int bb = threadIdx.x + u * NT;
+      pr[qd][u] = bb < nbIn ? partIn[qd * nbIn + bb] : 0.0;
     }
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gi = w % NG, sb = w / NG;
+  const int f = lane & 1;  // 0: A v_j, 1: A^dag w_j
+  const Cx<R>* in = f ? wj : vj;
+  const int s = (xcd_block() * NSB + sb) * 32 + (lane >> 1);
+  const bool live = s < g.V;
+  Cx<R> mine[M];
+  {
+    Cx<R> acc[1][12];
+    hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, acc);  // dead lanes hop at site 0
+    xput<NG>(xb, w, gi, lane, acc, mine);
   }
-  double v[2] = {dre, dim};
-  block_sum<2>(v);
-  if (threadIdx.x == 0) {
-    partOut[blockIdx.x] = v[0];
-    partOut[gridDim.x + blockIdx.x] = v[1];
-  }
-}
-
-// The same step with two lanes per site: the even lane computes A v_j, the
-// odd lane A^dag w_j.  Both lanes read the same link addresses in the same
-// instruction (one memory request), each lane needs half the registers of
-// the two-field version, and twice as many waves are in flight -- at 16^4 the
-// one-lane version leaves a single wave per SIMD to hide all load latency.
-template <class R, class LK>
-__global__ void __launch_bounds__(NT) k_bil1s(Geom g, LK lk, R diag, R eft, R ebt, int j,
-                                              const Cx<R>* __restrict__ vj, const Cx<R>* __restrict__ wj,
-                                              const Cx<R>* __restrict__ vjm1, const Cx<R>* __restrict__ wjm1,
-                                              Cx<R>* __restrict__ p, Cx<R>* __restrict__ q,
-                                              const double* __restrict__ partIn, int nbIn,
-                                              double* __restrict__ partOut, Coefs c) {
-  if (c.flags[0]) return;
+  if (flag) return;
   double red[4];
-  reduce_partials<4>(partIn, nbIn, red);
+#pragma unroll
+  for (int qd = 0; qd < 4; ++qd) red[qd] = pr[qd][0] + pr[qd][1];
+  block_sum<4>(red);  // also completes the exchange
   const C64 sdot = mk(red[0], red[1]);
   const double sabs = sqrt(norm2(sdot));
   if (j == 0 && !(sabs > 0.0 && sabs < 1e300)) {  // zero or non-finite source
@@ -297,32 +274,20 @@ __global__ void __launch_bounds__(NT) k_bil1s(Geom g, LK lk, R diag, R eft, R eb
       c.delta[j - 1] = mk(delta, 0.0);
     }
   }
-#if NK_FIELD_MAJOR
-  const int half = gridDim.x >> 1;
-  const int f = blockIdx.x >= half ? 1 : 0;  // 0: A v_j, 1: A^dag w_j
-  int hb = blockIdx.x - f * half;
-  if ((half & 7) == 0) hb = (hb & 7) * (half >> 3) + (hb >> 3);
-  const int s = hb * NT + threadIdx.x;
-#else
-  const int f = threadIdx.x & 1;  // 0: A v_j, 1: A^dag w_j
-  const int s = xcd_block() * (NT / 2) + (threadIdx.x >> 1);
-#endif
   const C64 scale = f ? swj : mk(svj, 0.0);
   const C64 sub = f ? delta * swjm1 : svjm1 * beta;  // delta_{j-1} sw_{j-1} or beta_{j-1} sv_{j-1}
-  const Cx<R>* in = f ? wj : vj;
   const Cx<R>* prev = f ? wjm1 : vjm1;
   Cx<R>* out = f ? q : p;
   double dre = 0.0, dim = 0.0;
-  if (s < g.V) {
-    Cx<R> acc[1][12];
-    const Cx<R>* ins[1] = {in};
-    const R ef[1] = {f ? ebt : eft};
-    const R eb[1] = {f ? eft : ebt};
-    hopping<R, 1>(g, s, lk, ins, ef, eb, acc);
+  if (live) {
+    int se = s;
+    asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
 #pragma unroll
-    for (int cc = 0; cc < 12; ++cc) {
-      const size_t i = (size_t)cc * g.V + s;
-      Cx<R> a = diag * in[i] - R(0.5) * acc[0][cc];
+    for (int cl = 0; cl < M; ++cl) {
+      const int cc = gi * M + cl;
+      const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
+      const size_t i = (size_t)cc * g.V + se;
+      Cx<R> a = diag * in[i] - R(0.5) * hs;
       if (cc >= 6) a = mk<R>(-a.re, -a.im);
       const C64 ad = widen(a);
       C64 o = cmul(scale, ad);
@@ -352,7 +317,29 @@ __global__ void __launch_bounds__(NT) k_bil2(int n, int j, const Cx<R>* __restri
                                              Cx<R>* __restrict__ vnext, Cx<R>* __restrict__ wnext,
                                              const double* __restrict__ partIn, int nbIn,
                                              double* __restrict__ partOut, Coefs c, LiftAcc lift) {
-  if (c.flags[0]) return;
+  // four elements per thread and batch: all loads of a batch are issued
+  // before its first store, which keeps enough bytes in flight to stream at
+  // full rate; the first batch is issued before the partial sums of K1 are
+  // reduced, so the reduction's latency overlaps the stream
+  constexpr int U = 4;
+  const int stride = gridDim.x * NT;
+  int i0 = blockIdx.x * NT + threadIdx.x;
+  Cx<R> pp[U], qq[U], vv[U], ww[U];
+  auto load = [&](int ib) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = ib + u * stride;
+      if (i < n) {
+        pp[u] = p[i];
+        qq[u] = q[i];
+        vv[u] = vj[i];
+        ww[u] = wj[i];
+      }
+    }
+  };
+  const int flag = c.flags[0];
+  load(i0);
+  if (flag) return;
   double red[2];
   reduce_partials<2>(partIn, nbIn, red);
   const double svj = c.sv[j];
@@ -364,22 +351,7 @@ __global__ void __launch_bounds__(NT) k_bil2(int n, int j, const Cx<R>* __restri
   const bool acc = lift.y && (j + 1 < lift.kused);
   const C64 lcn = acc ? lift.lc[j + 1] : mk(0.0, 0.0);
   double sre = 0.0, sim = 0.0, nv = 0.0, nw = 0.0;
-  // four elements per thread and iteration: all loads are issued before the
-  // first store, which keeps enough bytes in flight to stream at full rate
-  constexpr int U = 4;
-  const int stride = gridDim.x * NT;
-  for (int i0 = blockIdx.x * NT + threadIdx.x; i0 < n; i0 += U * stride) {
-    Cx<R> pp[U], qq[U], vv[U], ww[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 + u * stride;
-      if (i < n) {
-        pp[u] = p[i];
-        qq[u] = q[i];
-        vv[u] = vj[i];
-        ww[u] = wj[i];
-      }
-    }
+  for (; i0 < n; i0 += U * stride) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 + u * stride;
@@ -397,6 +369,7 @@ __global__ void __launch_bounds__(NT) k_bil2(int n, int j, const Cx<R>* __restri
         if (acc) lift.y[i] = lift.y[i] + cmul(lcn, vd);
       }
     }
+    if (i0 + U * stride < n) load(i0 + U * stride);
   }
   double v[4] = {sre, sim, nv, nw};
   block_sum<4>(v);
@@ -443,10 +416,12 @@ size_t basis_vector_bytes(const Geom& g, int prec) {
   return (size_t)12 * g.V * (prec == NK_PREC_FP64 ? sizeof(C64) : sizeof(C32));
 }
 
+// workgroups of the element-wise kernels; K1 prefetches at most 2 NT
+// partial sums per quantity, so this stays <= 2 NT
 static int nb_elem(const Geom& g) {
   const int n = 12 * g.V;
   int nb = (n + NT - 1) / NT;
-  return nb < 512 ? nb : 512;
+  return nb < 2 * NT ? nb : 2 * NT;
 }
 
 struct BasisBuffers {
@@ -471,7 +446,9 @@ static int get_buffers(nk_lattice* lat, const BasisPlan& bp, void* vk_ext, Basis
   b.q = w + b.colbytes;
   b.wring = w + 2 * b.colbytes;
   b.vk = bp.store ? (char*)vk_ext : w + 4 * b.colbytes;
-  const int nb1 = 2 * ((g.V + NT - 1) / NT) + 1, nb2 = nb_elem(g);
+  // K1 writes one partial per workgroup: at most one per 32 sites (k_bil1
+  // with four direction groups)
+  const int nb1 = (g.V + 31) / 32 + 1, nb2 = nb_elem(g);
   const int nbmax = nb1 > nb2 ? nb1 : nb2;
   if (lat->part.ensure((size_t)2 * 4 * nbmax * sizeof(double))) return NK_ENOMEM;
   b.partA = lat->part.as<double>();
@@ -513,9 +490,11 @@ static int run_steps(nk_lattice* lat, const BasisPlan& bp, const LK& lk, const C
                      BasisBuffers& b, LiftAcc lift, hipStream_t st) {
   const Geom& g = lat->g;
   const int n = 12 * g.V;
-  const int nb1 = (g.V + NT - 1) / NT, nb2 = nb_elem(g);
-  // two lanes per site; in field-major order each half of the grid covers all sites
-  const int nb1s = NK_FIELD_MAJOR ? 2 * ((g.V + NT - 1) / NT) : (2 * g.V + NT - 1) / NT;
+  constexpr int NG = NK_GROUPS;
+  // K1 workgroups: NT / 64 / NG blocks of 64 sites (Lanczos, one lane per
+  // site) or of 32 sites (two-sided, two lanes per site)
+  const int spb = (bp.hermitian ? 64 : 32) * ((NT / 64) / NG);
+  const int nb1 = (g.V + spb - 1) / spb, nb2 = nb_elem(g);
   const R diag = (R)(4.0 + bp.m_w);
   auto col = [&](int j) -> Cx<R>* {
     const int s = bp.store ? j : (j % 3);
@@ -538,36 +517,30 @@ static int run_steps(nk_lattice* lat, const BasisPlan& bp, const LK& lk, const C
   for (int j = j0; j < j1; ++j) {
     for (int kind = 0; kind < 2; ++kind) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (bp.profile) {
+      const bool timed = bp.profile > 0 && j % bp.profile == 0;
+      if (timed) {
         if (int r = prof_event(lat, &e0)) return r;
         if (int r = prof_event(lat, &e1)) return r;
       }
       if (bp.hermitian) {
         if (kind == 0)
-          hipExtLaunchKernelGGL((k_lan1<R, LK>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, j, col(j),
+          hipExtLaunchKernelGGL((k_lan1<R, LK, NG>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, j, col(j),
                                 j > 0 ? col(j - 1) : col(j), p, b.partB, nb2, b.partA, c);
         else
           hipExtLaunchKernelGGL((k_lan2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, col(j), col(j + 1),
                                 b.partA, nb1, b.partB, c, lift);
       } else {
         const R eft = (R)exp(bp.mu), ebt = (R)exp(-bp.mu);
-        const int nbk1 = NK_SPLIT_PAIR ? nb1s : nb1;
-        if (kind == 0) {
-          if (NK_SPLIT_PAIR)
-            hipExtLaunchKernelGGL((k_bil1s<R, LK>), dim3(nb1s), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j,
-                                  col(j), wsl(j), j > 0 ? col(j - 1) : col(j), j > 0 ? wsl(j - 1) : wsl(j), p, q,
-                                  b.partB, nb2, b.partA, c);
-          else
-            hipExtLaunchKernelGGL((k_bil1<R, LK>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j,
-                                  col(j), wsl(j), j > 0 ? col(j - 1) : col(j), j > 0 ? wsl(j - 1) : wsl(j), p, q,
-                                  b.partB, nb2, b.partA, c);
-        } else {
+        if (kind == 0)
+          hipExtLaunchKernelGGL((k_bil1<R, LK, NG>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j,
+                                col(j), wsl(j), j > 0 ? col(j - 1) : col(j), j > 0 ? wsl(j - 1) : wsl(j), p, q,
+                                b.partB, nb2, b.partA, c);
+        else
           hipExtLaunchKernelGGL((k_bil2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, q, col(j), wsl(j),
-                                col(j + 1), wsl(j + 1), b.partA, nbk1, b.partB, c, lift);
-        }
+                                col(j + 1), wsl(j + 1), b.partA, nb1, b.partB, c, lift);
       }
       NK_HIP(hipGetLastError());
-      if (bp.profile) lat->evkind.push_back(kind);
+      if (timed) lat->evkind.push_back(kind);
     }
   }
   return NK_OK;

@@ -181,9 +181,6 @@ __device__ __forceinline__ int nbr_bwd(const Geom& g, int s, const SiteC& c, boo
 #ifndef NK_HOP_FENCE
 #define NK_HOP_FENCE 1  // schedule each hop on its own (bounded registers)
 #endif
-#ifndef NK_HOP_ORDER
-#define NK_HOP_ORDER 0  // 0: x, y, z, t (forward then backward per direction); 1: all forward hops, then all backward
-#endif
 
 __device__ __forceinline__ void hop_fence() {
 #if NK_HOP_FENCE
@@ -201,6 +198,7 @@ __device__ __forceinline__ void hop_fwd(const Geom& g, int s, const SiteC& sc0, 
   const int sf = nbr_fwd<NU>(g, s, sc0, &wrap);
   const R bf = (NU == 3 && wrap) ? R(-1) : R(1);
   Cx<R> u[9];
+  Cx<R> h0[NF][3], h1[NF][3];
   hop_fence();
   lk.load(NU, s, u);
 #pragma unroll
@@ -208,16 +206,18 @@ __device__ __forceinline__ void hop_fwd(const Geom& g, int s, const SiteC& sc0, 
     Cx<R> p[12];
     load_spinor(in[f], V, sf, p);
     const R sc = bf * cf[f];
-    Cx<R> h0[3], h1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      h0[c] = sc * (p[c] + mulu<P::c0r, P::c0i>(p[P::p0 * 3 + c]));
-      h1[c] = sc * (p[3 + c] + mulu<P::c1r, P::c1i>(p[P::p1 * 3 + c]));
+      h0[f][c] = sc * (p[c] + mulu<P::c0r, P::c0i>(p[P::p0 * 3 + c]));
+      h1[f][c] = sc * (p[3 + c] + mulu<P::c1r, P::c1i>(p[P::p1 * 3 + c]));
     }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      Cx<R> g0 = cmul(u[a * 3 + 0], h0[0]) + cmul(u[a * 3 + 1], h0[1]) + cmul(u[a * 3 + 2], h0[2]);
-      Cx<R> g1 = cmul(u[a * 3 + 0], h1[0]) + cmul(u[a * 3 + 1], h1[1]) + cmul(u[a * 3 + 2], h1[2]);
+      Cx<R> g0 = cmul(u[a * 3 + 0], h0[f][0]) + cmul(u[a * 3 + 1], h0[f][1]) + cmul(u[a * 3 + 2], h0[f][2]);
+      Cx<R> g1 = cmul(u[a * 3 + 0], h1[f][0]) + cmul(u[a * 3 + 1], h1[f][1]) + cmul(u[a * 3 + 2], h1[f][2]);
       acc[f][a] = acc[f][a] + g0;
       acc[f][3 + a] = acc[f][3 + a] + g1;
       acc[f][P::p0 * 3 + a] = acc[f][P::p0 * 3 + a] + mulu<P::c0r, -P::c0i>(g0);
@@ -237,6 +237,7 @@ __device__ __forceinline__ void hop_bwd(const Geom& g, int s, const SiteC& sc0, 
   const int sb = nbr_bwd<NU>(g, s, sc0, &wrap);
   const R bb = (NU == 3 && wrap) ? R(-1) : R(1);
   Cx<R> u[9];
+  Cx<R> h0[NF][3], h1[NF][3];
   hop_fence();
   lk.load(NU, sb, u);
 #pragma unroll
@@ -244,16 +245,18 @@ __device__ __forceinline__ void hop_bwd(const Geom& g, int s, const SiteC& sc0, 
     Cx<R> p[12];
     load_spinor(in[f], V, sb, p);
     const R sc = bb * cb[f];
-    Cx<R> h0[3], h1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      h0[c] = sc * (p[c] - mulu<P::c0r, P::c0i>(p[P::p0 * 3 + c]));
-      h1[c] = sc * (p[3 + c] - mulu<P::c1r, P::c1i>(p[P::p1 * 3 + c]));
+      h0[f][c] = sc * (p[c] - mulu<P::c0r, P::c0i>(p[P::p0 * 3 + c]));
+      h1[f][c] = sc * (p[3 + c] - mulu<P::c1r, P::c1i>(p[P::p1 * 3 + c]));
     }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      Cx<R> g0 = cmulc(u[0 * 3 + a], h0[0]) + cmulc(u[1 * 3 + a], h0[1]) + cmulc(u[2 * 3 + a], h0[2]);
-      Cx<R> g1 = cmulc(u[0 * 3 + a], h1[0]) + cmulc(u[1 * 3 + a], h1[1]) + cmulc(u[2 * 3 + a], h1[2]);
+      Cx<R> g0 = cmulc(u[0 * 3 + a], h0[f][0]) + cmulc(u[1 * 3 + a], h0[f][1]) + cmulc(u[2 * 3 + a], h0[f][2]);
+      Cx<R> g1 = cmulc(u[0 * 3 + a], h1[f][0]) + cmulc(u[1 * 3 + a], h1[f][1]) + cmulc(u[2 * 3 + a], h1[f][2]);
       acc[f][a] = acc[f][a] + g0;
       acc[f][3 + a] = acc[f][3 + a] + g1;
       acc[f][P::p0 * 3 + a] = acc[f][P::p0 * 3 + a] - mulu<P::c0r, -P::c0i>(g0);
@@ -263,41 +266,110 @@ __device__ __forceinline__ void hop_bwd(const Geom& g, int s, const SiteC& sc0, 
   pin<R, NF>(acc);
 }
 
-// hop(x) for NF fields; eft/ebt are the forward/backward temporal factors of
-// each field (e^{+mu}, e^{-mu} for A(mu); swapped for A(-mu) = A(mu)^dag).
-template <class R, int NF, class LK>
-__device__ __forceinline__ void hopping(const Geom& g, int s, const LK& lk, const Cx<R>* const (&in)[NF],
-                                        const R (&eft)[NF], const R (&ebt)[NF], Cx<R> (&acc)[NF][12]) {
-  const SiteC x = site_coords(g, s);
-  const SiteC& y = x;
-  const SiteC& z = x;
-  const SiteC& t = x;
-  R one[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    one[f] = R(1);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[f][c] = mk<R>(0, 0);
-  }
-#if NK_HOP_ORDER == 0
-  hop_fwd<0>(g, s, x, lk, in, one, acc);
-  hop_bwd<0>(g, s, x, lk, in, one, acc);
-  hop_fwd<1>(g, s, y, lk, in, one, acc);
-  hop_bwd<1>(g, s, y, lk, in, one, acc);
-  hop_fwd<2>(g, s, z, lk, in, one, acc);
-  hop_bwd<2>(g, s, z, lk, in, one, acc);
-  hop_fwd<3>(g, s, t, lk, in, eft, acc);
-  hop_bwd<3>(g, s, t, lk, in, ebt, acc);
-#else
-  hop_fwd<0>(g, s, x, lk, in, one, acc);
-  hop_fwd<1>(g, s, y, lk, in, one, acc);
-  hop_fwd<2>(g, s, z, lk, in, one, acc);
-  hop_fwd<3>(g, s, t, lk, in, eft, acc);
-  hop_bwd<0>(g, s, x, lk, in, one, acc);
-  hop_bwd<1>(g, s, y, lk, in, one, acc);
-  hop_bwd<2>(g, s, z, lk, in, one, acc);
-  hop_bwd<3>(g, s, t, lk, in, ebt, acc);
+// --- direction groups over the waves of a workgroup -------------------------
+// The stencil kernels give each site's eight hops to NG waves of a 256-thread
+// workgroup: wave w takes direction group w % NG (NG = 4: one direction,
+// forward and backward hop; NG = 2: x and y, or z and t) for a block of sites.
+// The partial hopping sums then meet in LDS, where each wave finishes 12 / NG
+// of the 12 components, adding the groups in group order so that the result
+// does not depend on timing.  Against one lane doing all eight hops, the
+// eight hops of a site are in flight at once, and a workgroup covers NG times
+// fewer sites, so fewer sites are in flight per XCD and the neighbour spinors
+// and links they share are still in the XCD's L2 when the next site asks.
+
+#ifndef NK_GROUPS
+#define NK_GROUPS 4  // direction groups of the stencil kernels (2 or 4)
 #endif
+
+// hopping sum of direction group gi (wave-uniform) of one field at site s;
+// ef/eb are the forward/backward temporal factors
+template <int NG, class R, class LK>
+__device__ __forceinline__ void hop_group(const Geom& g, int s, const LK& lk, const Cx<R>* in, int gi, R ef, R eb,
+                                          Cx<R> (&acc)[1][12]) {
+  const SiteC x = site_coords(g, s);
+  const Cx<R>* ins[1] = {in};
+  const R one[1] = {R(1)};
+  const R f1[1] = {ef};
+  const R b1[1] = {eb};
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[0][c] = mk<R>(0, 0);
+  if (NG == 4) {
+    if (gi == 0) {
+      hop_fwd<0>(g, s, x, lk, ins, one, acc);
+      hop_bwd<0>(g, s, x, lk, ins, one, acc);
+    } else if (gi == 1) {
+      hop_fwd<1>(g, s, x, lk, ins, one, acc);
+      hop_bwd<1>(g, s, x, lk, ins, one, acc);
+    } else if (gi == 2) {
+      hop_fwd<2>(g, s, x, lk, ins, one, acc);
+      hop_bwd<2>(g, s, x, lk, ins, one, acc);
+    } else {
+      hop_fwd<3>(g, s, x, lk, ins, f1, acc);
+      hop_bwd<3>(g, s, x, lk, ins, b1, acc);
+    }
+  } else {
+    if (gi == 0) {
+      hop_fwd<0>(g, s, x, lk, ins, one, acc);
+      hop_bwd<0>(g, s, x, lk, ins, one, acc);
+      hop_fwd<1>(g, s, x, lk, ins, one, acc);
+      hop_bwd<1>(g, s, x, lk, ins, one, acc);
+    } else {
+      hop_fwd<2>(g, s, x, lk, ins, one, acc);
+      hop_bwd<2>(g, s, x, lk, ins, one, acc);
+      hop_fwd<3>(g, s, x, lk, ins, f1, acc);
+      hop_bwd<3>(g, s, x, lk, ins, b1, acc);
+    }
+  }
+}
+
+// LDS exchange of the partial hopping sums of the 4 waves of a workgroup
+template <class R, int NG>
+struct XBuf {
+  static constexpr int M = 12 / NG;  // components each wave finishes
+  Cx<R> v[4][12 - M][64];            // per wave: the components other waves finish
+};
+
+// slot of component cc in the buffer of group gg: below gg's own range it
+// keeps its index, above it moves down by M
+template <int NG>
+__device__ __forceinline__ int xslot(int cc, int gg) {
+  constexpr int M = 12 / NG;
+  return cc < gg * M ? cc : cc - M;
+}
+
+// wave w (group gi) hands the components other groups finish to LDS and keeps
+// its own share in mine[]
+template <int NG, class R>
+__device__ __forceinline__ void xput(XBuf<R, NG>& xb, int w, int gi, int lane, const Cx<R> (&acc)[1][12],
+                                     Cx<R> (&mine)[12 / NG]) {
+  constexpr int M = 12 / NG;
+#pragma unroll
+  for (int cc = 0; cc < 12; ++cc)
+    if (cc / M != gi) xb.v[w][xslot<NG>(cc, gi)][lane] = acc[0][cc];
+#pragma unroll
+  for (int cl = 0; cl < M; ++cl) {
+    mine[cl] = acc[0][cl];
+#pragma unroll
+    for (int gg = 1; gg < NG; ++gg)
+      if (gi == gg) mine[cl] = acc[0][gg * M + cl];
+  }
+}
+
+// after a workgroup barrier: the full hopping sum of component gi * M + cl of
+// the site block sb, summed over the groups in group order
+template <int NG, class R>
+__device__ __forceinline__ Cx<R> xsum(const XBuf<R, NG>& xb, int sb, int gi, int lane, int cl, const Cx<R>& mine) {
+  constexpr int M = 12 / NG;
+  const int cc = gi * M + cl;
+  Cx<R> hs = mk<R>(0, 0);
+#pragma unroll
+  for (int gg = 0; gg < NG; ++gg) {
+    if (gg == gi)
+      hs = hs + mine;
+    else
+      hs = hs + xb.v[sb * NG + gg][xslot<NG>(cc, gg)][lane];
+  }
+  return hs;
 }
 
 // gamma5 sign of component c = spin*3 + colour

@@ -5,23 +5,50 @@
 namespace nk {
 
 // y_f = [gamma5] ((4 + m_w) x_f - 1/2 hop(x_f)) for NF fields, device layout.
-template <class R, int NF, class LK>
+// Directions split over the waves of the workgroup (hop_group); NF lanes per
+// site, lane f on field f.
+template <class R, int NF, class LK, int NG>
 __global__ void __launch_bounds__(256) k_apply(Geom g, LK lk, R diag, int g5, FieldPtrs<R, NF> in,
                                                 FieldPtrsW<R, NF> out, TFac<R, NF> tf) {
-  const int s = xcd_block() * blockDim.x + threadIdx.x;
-  if (s >= g.V) return;
-  Cx<R> acc[NF][12];
-  hopping<R, NF>(g, s, lk, in.p, tf.f, tf.b, acc);
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      Cx<R> psi = in.p[f][(size_t)c * g.V + s];
-      Cx<R> o = diag * psi - R(0.5) * acc[f][c];
-      if (g5 && c >= 6) o = mk<R>(-o.re, -o.im);
-      out.p[f][(size_t)c * g.V + s] = o;
-    }
+  constexpr int M = 12 / NG;
+  constexpr int SPW = 64 / NF;         // sites per wave
+  constexpr int NSB = (256 / 64) / NG;  // site blocks per workgroup
+  __shared__ XBuf<R, NG> xb;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gi = w % NG, sb = w / NG;
+  const int f = NF == 1 ? 0 : lane & 1;
+  const Cx<R>* x = NF == 1 ? in.p[0] : (f ? in.p[NF - 1] : in.p[0]);
+  Cx<R>* y = NF == 1 ? out.p[0] : (f ? out.p[NF - 1] : out.p[0]);
+  const R ef = NF == 1 ? tf.f[0] : (f ? tf.f[NF - 1] : tf.f[0]);
+  const R eb = NF == 1 ? tf.b[0] : (f ? tf.b[NF - 1] : tf.b[0]);
+  const int s = (xcd_block() * NSB + sb) * SPW + lane / NF;
+  const bool live = s < g.V;
+  Cx<R> mine[M];
+  {
+    Cx<R> acc[1][12];
+    hop_group<NG>(g, live ? s : 0, lk, x, gi, ef, eb, acc);  // a lane past the end hops at site 0
+    xput<NG>(xb, w, gi, lane, acc, mine);
   }
+  __syncthreads();
+  if (!live) return;
+  int se = s;
+  asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
+#pragma unroll
+  for (int cl = 0; cl < M; ++cl) {
+    const int cc = gi * M + cl;
+    const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
+    const size_t i = (size_t)cc * g.V + se;
+    Cx<R> o = diag * x[i] - R(0.5) * hs;
+    if (g5 && cc >= 6) o = mk<R>(-o.re, -o.im);
+    y[i] = o;
+  }
+}
+
+// workgroups of k_apply for NF fields
+static int apply_blocks(const Geom& g, int nf) {
+  const int spb = (64 / nf) * ((256 / 64) / NK_GROUPS);
+  return (g.V + spb - 1) / spb;
 }
 
 static int check_gauge(nk_lattice* lat) {
@@ -39,8 +66,8 @@ int apply_dw_dev(nk_lattice* lat, double m_w, double mu, int g5, const C64* x, C
   FieldPtrsW<double, 1> out{{y}};
   TFac<double, 1> tf{{exp(mu)}, {exp(-mu)}};
   LinksPlain<double> lk{lat->U64.as<C64>(), g.V};
-  hipLaunchKernelGGL((k_apply<double, 1, LinksPlain<double>>), dim3((g.V + 255) / 256), dim3(256), 0, st, g, lk,
-                     4.0 + m_w, g5, in, out, tf);
+  hipLaunchKernelGGL((k_apply<double, 1, LinksPlain<double>, NK_GROUPS>), dim3(apply_blocks(g, 1)), dim3(256), 0,
+                     st, g, lk, 4.0 + m_w, g5, in, out, tf);
   NK_HIP(hipGetLastError());
   return NK_OK;
 }
@@ -53,8 +80,8 @@ int apply_pair_dev(nk_lattice* lat, double m_w, double mu, const C64* v, const C
   FieldPtrsW<double, 2> out{{av, adw}};
   TFac<double, 2> tf{{exp(mu), exp(-mu)}, {exp(-mu), exp(mu)}};
   LinksPlain<double> lk{lat->U64.as<C64>(), g.V};
-  hipLaunchKernelGGL((k_apply<double, 2, LinksPlain<double>>), dim3((g.V + 255) / 256), dim3(256), 0, st, g, lk,
-                     4.0 + m_w, 1, in, out, tf);
+  hipLaunchKernelGGL((k_apply<double, 2, LinksPlain<double>, NK_GROUPS>), dim3(apply_blocks(g, 2)), dim3(256), 0,
+                     st, g, lk, 4.0 + m_w, 1, in, out, tf);
   NK_HIP(hipGetLastError());
   return NK_OK;
 }
@@ -66,8 +93,8 @@ int apply_g5dw_prec(const Geom& g, const LK& lk, double m_w, double mu, const Cx
   FieldPtrs<R, 1> in{{x}};
   FieldPtrsW<R, 1> out{{y}};
   TFac<R, 1> tf{{(R)exp(mu)}, {(R)exp(-mu)}};
-  hipLaunchKernelGGL((k_apply<R, 1, LK>), dim3((g.V + 255) / 256), dim3(256), 0, st, g, lk, (R)(4.0 + m_w), 1,
-                     in, out, tf);
+  hipLaunchKernelGGL((k_apply<R, 1, LK, NK_GROUPS>), dim3(apply_blocks(g, 1)), dim3(256), 0, st, g, lk,
+                     (R)(4.0 + m_w), 1, in, out, tf);
   NK_HIP(hipGetLastError());
   return NK_OK;
 }
