@@ -63,7 +63,21 @@ typedef struct ihipStream_t* nk_stream_t; /* a hipStream_t */
 /* Roberts-Higham scaling */
 #define NK_RH_NONE 0    /* the paper's unscaled iteration, Eq. (4) */
 #define NK_RH_DET 1     /* mu_n = |det S_n|^{-1/n} */
-#define NK_RH_LEARNED 2 /* per-step factors predicted by the small MLP, falling back to NK_RH_DET */
+#define NK_RH_LEARNED 2 /* mu_n = |det S_n|^{-1/n} exp(y_n): determinant scaling times a correction
+                          predicted for the first NK_MLP_STEPS steps by the model installed with
+                          nk_rh_model_set (y = 0 later, for an implausible prediction and when no
+                          model is installed) */
+
+/* the learned-scaling network: NK_MLP_IN features -> 3 x NK_MLP_HIDDEN (tanh)
+ * -> NK_MLP_STEPS values y_n.  Flat FP32 parameters, in this order:
+ * W1[H][IN], b1[H], W2[H][H], b2[H], W3[H][H], b3[H], W4[STEPS][H], b4[STEPS]
+ * (NK_MLP_NTRAIN trainable values), then the feature standardisation
+ * mean[IN], inv_std[IN] (NK_MLP_NPARAMS in total). */
+#define NK_MLP_IN 16
+#define NK_MLP_HIDDEN 64
+#define NK_MLP_STEPS 4
+#define NK_MLP_NTRAIN 9668
+#define NK_MLP_NPARAMS 9700
 
 /* two-pass lift */
 #define NK_TWO_PASS_AUTO 0 /* store V_k when it fits in device memory, else two passes */
@@ -167,6 +181,56 @@ int nk_small_sign(int32_t k, int32_t ell, int32_t hermitian,
  * iters[b] the iteration counts.  scaling = NK_RH_*.  Synchronous. */
 int nk_rh_sign(int32_t batch, int32_t ld, const int32_t* n, double* S,
                int32_t scaling, int32_t maxit, double tol, int32_t* iters);
+
+/* The inner projection of Sec. 3: from a host tridiagonal H_k (layout as
+ * above), ell steps of Lanczos (hermitian != 0) or two-sided Lanczos on
+ * B = H_k + H_k^{-1} from e_1 (Eq. (6)), with full re-(bi)orthogonalisation.
+ * Writes the tridiagonal H_ell to host a[2 ell], b[2 ell], d[2 ell] (same
+ * layout as H_k) and its order to *ell_used (smaller than ell after an
+ * invariant subspace or a breakdown).  Synchronous. */
+int nk_inner_matrix(int32_t k, int32_t ell, int32_t hermitian,
+                    const double* alpha, const double* beta, const double* delta,
+                    double* a, double* b, double* d, int32_t* ell_used);
+
+/* --- learned Roberts-Higham scaling (an extension of Eq. (4)) -------------
+ * sgn(mu S) = sgn(S) for mu > 0 (the argument of Eq. (7) holds for mu z), so
+ * the factors change only the iteration count.  Training is label-free: for
+ * a diagonalisable S_0 each eigenvalue follows z <- (mu z + 1/(mu z)) / 2 and
+ * log|det S_n| = sum log|z|, and the loss is the smooth maximum over
+ * eigenvalues of log |z_T - sgn Re lambda| after NK_MLP_STEPS steps.
+ * All pointers below are device pointers (FP32 unless stated); every call
+ * is asynchronous on `stream`. */
+
+/* Install (host params[NK_MLP_NPARAMS]) or remove (NULL) the model used by
+ * NK_RH_LEARNED; process-wide, copied to the current device. */
+int nk_rh_model_set(const float* params);
+
+/* NK_MLP_IN features of each dense matrix: S device complex128 [batch][ld][ld]
+ * row-major, orders n (host int32[batch], n[b] <= ld); feat [batch][NK_MLP_IN]. */
+int nk_rh_features_device(int32_t batch, int32_t ld, const int32_t* n, const void* S, float* feat,
+                          nk_stream_t stream);
+
+/* Forward pass: y [batch][NK_MLP_STEPS]; act [batch][3][NK_MLP_HIDDEN]
+ * keeps the hidden activations for the backward pass (may be NULL). */
+int nk_mlp_forward_device(int32_t batch, const float* params, const float* feat, float* y, float* act,
+                          nk_stream_t stream);
+
+/* Spectral loss per sample and its gradient times gscale:
+ * eigenvalues of sample b are lam[off[b] .. off[b+1]) (device complex128;
+ * off device int32[batch + 1], at most 1024 per sample); loss [batch];
+ * dy [batch][NK_MLP_STEPS] = gscale * dloss_b / dy_b. */
+int nk_rh_spectral_loss_device(int32_t batch, const int32_t* off, const void* lam, const float* y,
+                               float gscale, float* loss, float* dy, nk_stream_t stream);
+
+/* Backward pass: grad [NK_MLP_NTRAIN] = sum_b d<dy_b, y_b>/dparams, summed
+ * over the batch in a fixed order; delta is workspace [batch][3][NK_MLP_HIDDEN]. */
+int nk_mlp_backward_device(int32_t batch, const float* params, const float* feat, const float* act,
+                           const float* dy, float* delta, float* grad, nk_stream_t stream);
+
+/* One Adam step on params[0 .. n) (n <= NK_MLP_NTRAIN normally) with moment
+ * buffers m, v; t counts steps from 1. */
+int nk_adam_step_device(int32_t n, float* params, const float* grad, float* m, float* v, int32_t t,
+                        float lr, float beta1, float beta2, float eps, nk_stream_t stream);
 
 /* y ~ sgn(gamma5 Dw(mu)) x (Eqs. (3)-(6)), nrhs canonical host vectors.
  * Synchronous.  NK_WARN_* on a valid but unconverged/broken-down result.

@@ -122,3 +122,21 @@ def uneven_ell(nsrc: int = 32, lo: int = 40, hi: int = 300, seed: int = 0) -> np
     """Per-source inner Krylov sizes drawn uniformly from [lo, hi]."""
     rng = np.random.default_rng([seed, 2])
     return rng.integers(lo, hi + 1, nsrc)
+
+
+def mlp_init(seed: int = 0, nin: int = 16, nh: int = 64, nout: int = 4) -> np.ndarray:
+    """Seeded initial parameters of a nin-nh-nh-nh-nout network, flat float32 in
+    the order W1, b1, W2, b2, W3, b3, W4, b4 followed by the feature
+    standardisation (mean = 0, inverse std = 1).  Hidden weights are uniform
+    with the Glorot bound sqrt(6 / (fan_in + fan_out)); the output layer and
+    all biases start at zero (the untrained network outputs 0).  Random
+    numbers only, no arithmetic of the method."""
+    rng = np.random.default_rng([seed, 7])
+    parts = []
+    for fi, fo, gain in ((nin, nh, 1.0), (nh, nh, 1.0), (nh, nh, 1.0), (nh, nout, 0.0)):
+        bound = gain * np.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-bound, bound, size=fo * fi))
+        parts.append(np.zeros(fo))
+    parts.append(np.zeros(nin))
+    parts.append(np.ones(nin))
+    return np.concatenate(parts).astype(np.float32)

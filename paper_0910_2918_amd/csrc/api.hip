@@ -127,12 +127,12 @@ static int estimate(int kk, int ell, int herm, int d, const nk_sign_params* p, C
   std::vector<C64> z1(kk), z0(kk - d);
   SmallOut so;
   int e = small_sign_dev(kk, ell, herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling, p->rh_maxit, p->rh_tol,
-                         cb.z0, &so, st, nullptr, 0);
+                         cb.z0, &so, st);
   if (e < 0) return e;
   NK_HIP(hipMemcpyAsync(z1.data(), cb.z0, kk * sizeof(C64), hipMemcpyDeviceToHost, st));
   NK_HIP(hipStreamSynchronize(st));
   e = small_sign_dev(kk - d, std::min(ell, kk - d), herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling,
-                     p->rh_maxit, p->rh_tol, cb.z0, &so, st, nullptr, 0);
+                     p->rh_maxit, p->rh_tol, cb.z0, &so, st);
   if (e < 0) return e;
   NK_HIP(hipMemcpyAsync(z0.data(), cb.z0, (kk - d) * sizeof(C64), hipMemcpyDeviceToHost, st));
   NK_HIP(hipStreamSynchronize(st));
@@ -227,7 +227,7 @@ static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64
   }
   SmallOut so;
   int es = small_sign_dev(kused, std::min(ell, kused), herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling,
-                          p->rh_maxit, p->rh_tol, cb.z, &so, st, nullptr, 0);
+                          p->rh_maxit, p->rh_tol, cb.z, &so, st);
   if (es < 0) return es;
   if (es > 0 && warn == NK_OK) warn = es;
   if (p->est_delay > 0 && std::isnan(est) && kused - p->est_delay >= 1) {
@@ -490,7 +490,7 @@ int nk_small_sign(int32_t k, int32_t ell, int32_t hermitian, const double* alpha
   NK_HIP(hipMemcpy(a + 2 * k, delta, k * sizeof(C64), hipMemcpyHostToDevice));
   SmallOut so;
   int e = small_sign_dev(k, ell, hermitian, a, a + k, a + 2 * k, p->rh_scaling, p->rh_maxit, p->rh_tol, a + 3 * k,
-                         &so, nullptr, nullptr, 0);
+                         &so, nullptr);
   if (e < 0) return e;
   NK_HIP(hipMemcpy(z, a + 3 * k, k * sizeof(C64), hipMemcpyDeviceToHost));
   if (info) {
@@ -504,9 +504,96 @@ int nk_small_sign(int32_t k, int32_t ell, int32_t hermitian, const double* alpha
   return e;
 }
 
+int nk_inner_matrix(int32_t k, int32_t ell, int32_t hermitian, const double* alpha, const double* beta,
+                    const double* delta, double* a, double* b, double* d, int32_t* ell_used) {
+  if (k < 1 || ell < 1 || ell > k || !alpha || !beta || !delta || !a || !b || !d || !ell_used) {
+    set_error("invalid argument to nk_inner_matrix");
+    return NK_EINVAL;
+  }
+  DevBuf buf;
+  if (buf.ensure((size_t)4 * k * sizeof(C64))) return NK_ENOMEM;
+  C64* c = buf.as<C64>();
+  NK_HIP(hipMemcpy(c, alpha, k * sizeof(C64), hipMemcpyHostToDevice));
+  NK_HIP(hipMemcpy(c + k, beta, k * sizeof(C64), hipMemcpyHostToDevice));
+  NK_HIP(hipMemcpy(c + 2 * k, delta, k * sizeof(C64), hipMemcpyHostToDevice));
+  std::vector<C64> hl((size_t)3 * ell);
+  SmallOut so;
+  so.hl_host = hl.data();
+  so.inner_only = true;
+  const int e = small_sign_dev(k, ell, hermitian, c, c + k, c + 2 * k, NK_RH_NONE, 1, 0.0, c + 3 * k, &so, nullptr);
+  if (e < 0) return e;
+  const int lu = so.ell_used;
+  std::memset(a, 0, 2 * sizeof(double) * ell);
+  std::memset(b, 0, 2 * sizeof(double) * ell);
+  std::memset(d, 0, 2 * sizeof(double) * ell);
+  std::memcpy(a, hl.data(), lu * sizeof(C64));
+  std::memcpy(b, hl.data() + lu, lu * sizeof(C64));
+  std::memcpy(d, hl.data() + 2 * lu, lu * sizeof(C64));
+  *ell_used = lu;
+  return e;
+}
+
+int nk_rh_model_set(const float* params) { return nk::mlp_model_set(params); }
+
+int nk_rh_features_device(int32_t batch, int32_t ld, const int32_t* n, const void* S, float* feat,
+                          nk_stream_t stream) {
+  if (batch < 1 || ld < 1 || !n || !S || !feat) {
+    set_error("invalid argument to nk_rh_features_device");
+    return NK_EINVAL;
+  }
+  for (int b = 0; b < batch; ++b)
+    if (n[b] < 1 || n[b] > ld) {
+      set_error("matrix %d has size %d outside [1, ld=%d]", b, n[b], ld);
+      return NK_EINVAL;
+    }
+  DevBuf nb;
+  if (nb.ensure((size_t)batch * sizeof(int))) return NK_ENOMEM;
+  NK_HIP(hipMemcpyAsync(nb.p, n, batch * sizeof(int), hipMemcpyHostToDevice, stream));
+  if (int e = mlp_features(batch, ld, nb.as<int>(), (const C64*)S, feat, stream)) return e;
+  NK_HIP(hipStreamSynchronize(stream));  // nb is released on return
+  return NK_OK;
+}
+
+int nk_mlp_forward_device(int32_t batch, const float* params, const float* feat, float* y, float* act,
+                          nk_stream_t stream) {
+  if (batch < 0 || !params || (batch > 0 && (!feat || !y))) {
+    set_error("invalid argument to nk_mlp_forward_device");
+    return NK_EINVAL;
+  }
+  return mlp_forward(batch, params, feat, y, act, stream);
+}
+
+int nk_rh_spectral_loss_device(int32_t batch, const int32_t* off, const void* lam, const float* y, float gscale,
+                               float* loss, float* dy, nk_stream_t stream) {
+  if (batch < 0 || (batch > 0 && (!off || !lam || !y || !loss || !dy))) {
+    set_error("invalid argument to nk_rh_spectral_loss_device");
+    return NK_EINVAL;
+  }
+  return mlp_spectral_loss(batch, off, (const C64*)lam, y, gscale, loss, dy, stream);
+}
+
+int nk_mlp_backward_device(int32_t batch, const float* params, const float* feat, const float* act,
+                           const float* dy, float* delta, float* grad, nk_stream_t stream) {
+  if (batch < 0 || !params || !grad || (batch > 0 && (!feat || !act || !dy || !delta))) {
+    set_error("invalid argument to nk_mlp_backward_device");
+    return NK_EINVAL;
+  }
+  return mlp_backward(batch, params, feat, act, dy, delta, grad, stream);
+}
+
+int nk_adam_step_device(int32_t n, float* params, const float* grad, float* m, float* v, int32_t t, float lr,
+                        float beta1, float beta2, float eps, nk_stream_t stream) {
+  if (n < 0 || t < 1 || (n > 0 && (!params || !grad || !m || !v))) {
+    set_error("invalid argument to nk_adam_step_device");
+    return NK_EINVAL;
+  }
+  if (n == 0) return NK_OK;
+  return mlp_adam(n, params, grad, m, v, t, lr, beta1, beta2, eps, stream);
+}
+
 int nk_rh_sign(int32_t batch, int32_t ld, const int32_t* n, double* S, int32_t scaling, int32_t maxit, double tol,
                int32_t* iters) {
-  if (batch < 1 || ld < 1 || !n || !S || !iters || maxit < 1 || scaling < 0 || scaling > 1) {
+  if (batch < 1 || ld < 1 || !n || !S || !iters || maxit < 1 || scaling < 0 || scaling > 2) {
     set_error("invalid argument to nk_rh_sign");
     return NK_EINVAL;
   }
@@ -519,7 +606,7 @@ int nk_rh_sign(int32_t batch, int32_t ld, const int32_t* n, double* S, int32_t s
   const size_t bytes = (size_t)batch * ld * ld * sizeof(C64);
   if (buf.ensure(bytes)) return NK_ENOMEM;
   NK_HIP(hipMemcpy(buf.p, S, bytes, hipMemcpyHostToDevice));
-  int e = rh_sign_batched(batch, ld, n, buf.as<C64>(), scaling, maxit, tol, iters, nullptr, nullptr, nullptr, 0);
+  int e = rh_sign_batched(batch, ld, n, buf.as<C64>(), scaling, maxit, tol, iters, nullptr, nullptr);
   if (e < 0) return e;
   NK_HIP(hipMemcpy(S, buf.p, bytes, hipMemcpyDeviceToHost));
   return e;

@@ -188,15 +188,28 @@ struct SmallOut {
   int rh_iters = 0;
   int ell_used = 0;
   double rh_residual = 0;
+  C64* hl_host = nullptr;  // if set: receives H_ell's diagonal, super- and sub-diagonal (3 x ell, host)
+  bool inner_only = false; // stop after the inner projection (no Roberts-Higham, no lift)
 };
-// mu_sched: optional host array [mu_steps] of Roberts-Higham scale factors (NK_RH_LEARNED)
 int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,
-                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st,
-                   const double* mu_sched, int mu_steps);
+                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st);
 
 // rh.hip -- batched Roberts-Higham on dense matrices (S on the device, row-major,
-// matrix b at b * ld * ld); mu_sched: host [batch][mu_steps] factors for NK_RH_LEARNED
+// matrix b at b * ld * ld)
 int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
-                    int* iters_host, double* resid_host, hipStream_t st, const double* mu_sched, int mu_steps);
+                    int* iters_host, double* resid_host, hipStream_t st);
+
+// mlp.hip -- learned Roberts-Higham scaling (device pointers)
+int mlp_features(int batch, int ld, const int* nvec_dev, const C64* S, float* feat, hipStream_t st);
+int mlp_forward(int batch, const float* P, const float* feat, float* y, float* act, hipStream_t st);
+int mlp_spectral_loss(int batch, const int* off, const C64* lam, const float* y, float gscale, float* loss,
+                      float* dy, hipStream_t st);
+int mlp_backward(int batch, const float* P, const float* feat, const float* act, const float* dy, float* delta,
+                 float* grad, hipStream_t st);
+int mlp_adam(int n, float* p, const float* g, float* m, float* v, int t, float lr, float b1, float b2, float eps,
+             hipStream_t st);
+int mlp_model_set(const float* params_host);
+// [batch][NK_MLP_STEPS] FP64 factors (-1 = fall back) from the installed model; *have = 0 without one
+int mlp_schedule(int batch, int ld, const int* nvec_dev, const C64* S, double* mu_dev, int* have, hipStream_t st);
 
 }  // namespace nk

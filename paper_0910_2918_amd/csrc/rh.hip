@@ -268,8 +268,8 @@ __global__ void __launch_bounds__(256) k_rh_combine(int ld, int nb, const int* _
   double dsum = 0.0, nsum = 0.0;
   if (active[b]) {
     double mu = 1.0;
-    if (scaling == NK_RH_DET) mu = exp(-logdet[b] / n);
-    else if (scaling == NK_RH_LEARNED && mu_in && mu_in[b] > 0.0) mu = mu_in[b];
+    if (scaling == NK_RH_DET || scaling == NK_RH_LEARNED) mu = exp(-logdet[b] / n);
+    if (scaling == NK_RH_LEARNED && mu_in && mu_in[b] > 0.0) mu *= mu_in[b];  // learned correction
     const double imu = 1.0 / mu;
     const size_t off = (size_t)b * ld * ld;
     const int npan = (n + nb - 1) / nb;
@@ -448,9 +448,9 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
     // S_{n+1} = (mu S_n + (mu S_n)^{-1}) / 2, inv[pos(r)][rowof(c)] held at (r, c)
     double mu = 1.0;
     if (scaling == NK_RH_DET) mu = exp(-logdet / n);
-    if (scaling == NK_RH_LEARNED) {
+    if (scaling == NK_RH_LEARNED) {  // determinant scaling times the learned correction of this step
       const double m = (mu_sched && it - 1 < mu_steps) ? mu_sched[(size_t)b * mu_steps + (it - 1)] : -1.0;
-      mu = m > 0.0 ? m : exp(-logdet / n);
+      mu = exp(-logdet / n) * (m > 0.0 ? m : 1.0);
     }
     const double imu = 1.0 / mu;
     double dsum = 0.0, nsum = 0.0;
@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
 // ---------------------------------------------------------------------------
 namespace {
 std::mutex g_rh_mu;
-DevBuf g_G0, g_G1, g_int, g_dbl, g_mu;
+DevBuf g_G0, g_G1, g_int, g_dbl, g_mu, g_sched;
 }  // namespace
 
 template <int NB, int RM>
@@ -522,7 +522,7 @@ static void launch_inverse(int batch, int ld, int maxn, const int* nvec, const i
 }
 
 int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
-                    int* iters_host, double* resid_host, hipStream_t st, const double* mu_sched, int mu_steps) {
+                    int* iters_host, double* resid_host, hipStream_t st) {
   std::lock_guard<std::mutex> lock(g_rh_mu);
   if (batch <= 0 || ld <= 0) return NK_OK;
   if (ld > 4 * PT) {
@@ -547,15 +547,19 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   int maxn = 0;
   std::vector<int> act_h(batch), zeros(batch, 0);
   for (int b = 0; b < batch; ++b) maxn = std::max(maxn, n_host[b]);
+  NK_HIP(hipMemcpyAsync(nvec, n_host, batch * sizeof(int), hipMemcpyHostToDevice, st));
+  // learned scaling: the installed model's factors for the first steps of
+  // each matrix, predicted from S_0 (without a model: determinant scaling)
+  const int mu_steps = NK_MLP_STEPS;
+  const double* mdev = nullptr;
+  if (scaling == NK_RH_LEARNED) {
+    if (g_sched.ensure((size_t)batch * mu_steps * sizeof(double))) return NK_ENOMEM;
+    int have = 0;
+    if (int e = mlp_schedule(batch, ld, nvec, S, g_sched.as<double>(), &have, st)) return e;
+    if (have) mdev = g_sched.as<double>();
+  }
   if (maxn <= SMAX) {
-    NK_HIP(hipMemcpyAsync(nvec, n_host, batch * sizeof(int), hipMemcpyHostToDevice, st));
     NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
-    const double* mdev = nullptr;
-    if (scaling == NK_RH_LEARNED && mu_sched && mu_steps > 0) {
-      if (g_mu.ensure((size_t)batch * mu_steps * sizeof(double))) return NK_ENOMEM;
-      NK_HIP(hipMemcpyAsync(g_mu.p, mu_sched, (size_t)batch * mu_steps * sizeof(double), hipMemcpyHostToDevice, st));
-      mdev = g_mu.as<double>();
-    }
     int rps = 0;  // largest rows-per-thread over the batch
     for (int b = 0; b < batch; ++b)
       if (n_host[b] > 0) rps = std::max(rps, (n_host[b] + ST_RH / n_host[b] - 1) / (ST_RH / n_host[b]));
@@ -587,9 +591,14 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     act_h[b] = n_host[b] > 0 ? 1 : 0;
     iters_host[b] = 0;
   }
-  NK_HIP(hipMemcpyAsync(nvec, n_host, batch * sizeof(int), hipMemcpyHostToDevice, st));
   NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
   std::vector<double> prev(batch, INFINITY), part_h((size_t)batch * nbl * 2), mu_h(batch, 1.0);
+  std::vector<double> sched_h;
+  if (mdev) {
+    sched_h.resize((size_t)batch * mu_steps);
+    NK_HIP(hipMemcpyAsync(sched_h.data(), mdev, sched_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipStreamSynchronize(st));
+  }
   for (int it = 1; it <= maxit; ++it) {
     bool any = false;
     for (int b = 0; b < batch; ++b) any = any || act_h[b];
@@ -597,7 +606,7 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     NK_HIP(hipMemcpyAsync(act, act_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
     if (scaling == NK_RH_LEARNED) {
       for (int b = 0; b < batch; ++b)
-        mu_h[b] = (mu_sched && it - 1 < mu_steps) ? mu_sched[(size_t)b * mu_steps + (it - 1)] : -1.0;
+        mu_h[b] = (mdev && it - 1 < mu_steps) ? sched_h[(size_t)b * mu_steps + (it - 1)] : -1.0;
       NK_HIP(hipMemcpyAsync(mu_dev, mu_h.data(), batch * sizeof(double), hipMemcpyHostToDevice, st));
     }
     hipLaunchKernelGGL(k_rh_start, dim3((maxn + 255) / 256, batch), dim3(256), 0, st, ld, batch, nvec, act, perm,

@@ -419,8 +419,7 @@ DevBuf g_small;
 }
 
 int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,
-                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st,
-                   const double* mu_sched, int mu_steps) {
+                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st) {
   if (k <= 0) return NK_EINVAL;
   if (ell > k) ell = k;
   if (ell <= 0) {
@@ -431,7 +430,7 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     NK_HIP(hipGetLastError());
     int it = 0;
     double res = 0;
-    int e = rh_sign_batched(1, k, &k, H, rh_scaling, rh_maxit, rh_tol, &it, &res, st, mu_sched, mu_steps);
+    int e = rh_sign_batched(1, k, &k, H, rh_scaling, rh_maxit, rh_tol, &it, &res, st);
     if (e < 0) return e;
     hipLaunchKernelGGL(k_col0, dim3((k + 255) / 256), dim3(256), 0, st, k, H, z);
     NK_HIP(hipGetLastError());
@@ -524,11 +523,21 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     return NK_WARN_NOTCONV;
   }
   const int lu = fl[0] ? fl[0] : ell;
+  if (out && out->hl_host) {
+    NK_HIP(hipMemcpyAsync(out->hl_host, s.a, lu * sizeof(C64), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(out->hl_host + lu, s.b, lu * sizeof(C64), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(out->hl_host + 2 * lu, s.d, lu * sizeof(C64), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipStreamSynchronize(st));
+  }
+  if (out && out->inner_only) {
+    out->ell_used = lu;
+    return fl[0] ? NK_WARN_BREAKDOWN : NK_OK;
+  }
   hipLaunchKernelGGL(k_tri_dense, dim3(256), dim3(256), 0, st, lu, s.a, s.b, s.d, Hl);
   NK_HIP(hipGetLastError());
   int it = 0;
   double res = 0;
-  int e = rh_sign_batched(1, lu, &lu, Hl, rh_scaling, rh_maxit, rh_tol, &it, &res, st, mu_sched, mu_steps);
+  int e = rh_sign_batched(1, lu, &lu, Hl, rh_scaling, rh_maxit, rh_tol, &it, &res, st);
   if (e < 0) return e;
   hipLaunchKernelGGL(k_in_lift, dim3((k + 255) / 256), dim3(256), 0, st, k, lu, s.V, Hl, lu, z);
   NK_HIP(hipGetLastError());

@@ -32,6 +32,12 @@ NK_RH_NONE = 0
 NK_RH_DET = 1
 NK_RH_LEARNED = 2
 
+NK_MLP_IN = 16
+NK_MLP_HIDDEN = 64
+NK_MLP_STEPS = 4
+NK_MLP_NTRAIN = 9668
+NK_MLP_NPARAMS = 9700
+
 NK_TWO_PASS_AUTO = 0
 NK_TWO_PASS_ON = 1
 NK_TWO_PASS_OFF = 2
@@ -49,6 +55,13 @@ EXPORTS = (
     "nk_krylov_basis_device",
     "nk_small_sign",
     "nk_rh_sign",
+    "nk_inner_matrix",
+    "nk_rh_model_set",
+    "nk_rh_features_device",
+    "nk_mlp_forward_device",
+    "nk_rh_spectral_loss_device",
+    "nk_mlp_backward_device",
+    "nk_adam_step_device",
     "nk_sign_apply",
     "nk_sign_apply_device",
     "nk_last_error",
@@ -139,6 +152,13 @@ def library():
         "nk_krylov_basis_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, vp, vp, P(nk_sign_info), vp]),
         "nk_small_sign": (C.c_int, [i32, i32, i32, vp, vp, vp, P(nk_sign_params), vp, P(nk_sign_info)]),
         "nk_rh_sign": (C.c_int, [i32, i32, P(i32), vp, i32, i32, dbl, P(i32)]),
+        "nk_inner_matrix": (C.c_int, [i32, i32, i32, vp, vp, vp, vp, vp, vp, P(i32)]),
+        "nk_rh_model_set": (C.c_int, [vp]),
+        "nk_rh_features_device": (C.c_int, [i32, i32, P(i32), vp, vp, vp]),
+        "nk_mlp_forward_device": (C.c_int, [i32, vp, vp, vp, vp, vp]),
+        "nk_rh_spectral_loss_device": (C.c_int, [i32, vp, vp, vp, C.c_float, vp, vp, vp]),
+        "nk_mlp_backward_device": (C.c_int, [i32, vp, vp, vp, vp, vp, vp, vp]),
+        "nk_adam_step_device": (C.c_int, [i32, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
         "nk_sign_apply": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info)]),
         "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
         "nk_last_error": (C.c_char_p, []),
@@ -276,6 +296,79 @@ def nk_rh_sign(S: np.ndarray, n=None, scaling: int = NK_RH_NONE, maxit: int = 10
     it = (C.c_int32 * batch)()
     rc = _check(library().nk_rh_sign(batch, ld, nn, _hptr(S), scaling, maxit, tol, it))
     return S, np.array(list(it)), rc
+
+
+def nk_inner_matrix(k: int, ell: int, hermitian: bool, alpha, beta, delta):
+    """H_ell of the inner projection (Sec. 3); returns (a, b, d, ell_used, rc)."""
+    al = np.zeros(k, np.complex128)
+    be = np.zeros(k, np.complex128)
+    de = np.zeros(k, np.complex128)
+    al[:k] = np.asarray(alpha)[:k]
+    nb = min(len(beta), k)
+    be[:nb] = np.asarray(beta)[:nb]
+    de[:nb] = np.asarray(delta)[:nb]
+    a = np.zeros(ell, np.complex128)
+    b = np.zeros(ell, np.complex128)
+    d = np.zeros(ell, np.complex128)
+    lu = C.c_int32()
+    rc = _check(library().nk_inner_matrix(k, ell, 1 if hermitian else 0, _hptr(al), _hptr(be), _hptr(de), _hptr(a),
+                                          _hptr(b), _hptr(d), C.byref(lu)))
+    n = lu.value
+    return a[:n], b[:n], d[:n], n, rc
+
+
+def _fptr(t):
+    """Device pointer of a contiguous float32 CUDA tensor."""
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch.float32":
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _iptr(t):
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch.int32":
+        raise ValueError("expected a contiguous int32 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def nk_rh_model_set(params) -> None:
+    """Install (float32 array of NK_MLP_NPARAMS) or remove (None) the NK_RH_LEARNED model."""
+    if params is None:
+        _check(library().nk_rh_model_set(None))
+        return
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    if a.size != NK_MLP_NPARAMS:
+        raise ValueError(f"expected {NK_MLP_NPARAMS} parameters")
+    _check(library().nk_rh_model_set(C.c_void_p(a.ctypes.data)))
+
+
+def nk_rh_features_device(S, n, feat, stream=None) -> None:
+    """S: (batch, ld, ld) complex128 CUDA tensor; n: host sizes; feat: (batch, 16) float32 CUDA tensor."""
+    batch, ld = S.shape[0], S.shape[1]
+    nn = (C.c_int32 * batch)(*[int(e) for e in n])
+    _check(library().nk_rh_features_device(batch, ld, nn, _dptr(S), _fptr(feat), _stream(stream)))
+
+
+def nk_mlp_forward_device(params, feat, y, act=None, stream=None) -> None:
+    batch = feat.shape[0]
+    _check(library().nk_mlp_forward_device(batch, _fptr(params), _fptr(feat), _fptr(y),
+                                           None if act is None else _fptr(act), _stream(stream)))
+
+
+def nk_rh_spectral_loss_device(off, lam, y, gscale, loss, dy, stream=None) -> None:
+    batch = y.shape[0]
+    _check(library().nk_rh_spectral_loss_device(batch, _iptr(off), _dptr(lam), _fptr(y), float(gscale), _fptr(loss),
+                                                _fptr(dy), _stream(stream)))
+
+
+def nk_mlp_backward_device(params, feat, act, dy, delta, grad, stream=None) -> None:
+    batch = feat.shape[0]
+    _check(library().nk_mlp_backward_device(batch, _fptr(params), _fptr(feat), _fptr(act), _fptr(dy), _fptr(delta),
+                                            _fptr(grad), _stream(stream)))
+
+
+def nk_adam_step_device(n, params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None) -> None:
+    _check(library().nk_adam_step_device(int(n), _fptr(params), _fptr(grad), _fptr(m), _fptr(v), int(t), float(lr),
+                                         float(beta1), float(beta2), float(eps), _stream(stream)))
 
 
 def nk_sign_apply(h, params: nk_sign_params, x: np.ndarray):

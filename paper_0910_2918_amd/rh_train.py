@@ -1,0 +1,248 @@
+"""Training of the learned Roberts-Higham scaling on the GPU.
+
+The matrices are the small Ritz matrices H_ell that the method itself builds
+(the inner projection of Sec. 3 on B = H_k + H_k^{-1}, Eq. (6)): the outer
+basis runs on the GPU (nk_krylov_basis_device), the inner projection too
+(nk_inner_matrix), and the leading blocks of one inner run give H_ell for
+every smaller ell.  Training uses the library's own kernels only -- features,
+forward pass, spectral loss, backward pass and Adam -- driven from here
+through the C ABI.  The eigenvalues the label-free loss needs are computed
+once per matrix when the data set is prepared (numpy), outside the path.
+
+    python -m paper_0910_2918_amd.rh_train --out paper_0910_2918_amd/rh_scaling_weights.npy
+
+writes the trained parameters (float32, NK_MLP_NPARAMS) that NK_RH_LEARNED
+uses once installed with nk_rh_model_set.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if _ROOT not in sys.path:
+    sys.path.insert(0, _ROOT)
+
+from paper_0910_2918_amd import nk  # noqa: E402
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rh_scaling_weights.npy")
+
+# (dims, mu, link width, outer k, largest inner ell, gauge fields, sources per
+# field): the workloads of the 4^4, 8^4 and 16^4 runs
+CONFIGS = [
+    ((4, 4, 4, 4), 0.0, 0.4, 150, 120, 8, 2),
+    ((8, 8, 8, 8), 0.3, 0.6, 400, 200, 6, 2),
+    ((8, 8, 8, 8), 0.0, 0.6, 400, 200, 4, 2),
+    ((16, 16, 16, 16), 0.3, 0.8, 600, 300, 3, 1),
+    ((16, 16, 16, 16), 0.0, 0.8, 600, 300, 3, 1),
+]
+
+
+def tridiag_dense(a, b, d) -> np.ndarray:
+    n = len(a)
+    h = np.diag(np.asarray(a, np.complex128))
+    if n > 1:
+        h += np.diag(np.asarray(b[:n - 1], np.complex128), 1) + np.diag(np.asarray(d[:n - 1], np.complex128), -1)
+    return h
+
+
+def collect(configs=CONFIGS, ell_min: int = 16, ell_step: int = 2, seed0: int = 0, log=print):
+    """Dense H_ell matrices from GPU runs of the method: one list per (config,
+    gauge field), so that whole gauge fields can be held out."""
+    import torch
+
+    import latgen
+
+    out = []
+    for ci, (dims, mu, eps, k, lmax, ngauge, nsrc) in enumerate(configs):
+        t0 = time.time()
+        count = 0
+        for gi in range(ngauge):
+            mats = []
+            gseed = seed0 + 1000 * ci + gi
+            with nk.Lattice(dims) as lat:
+                nk.nk_gauge_set(lat.h, latgen.random_gauge(dims, eps, gseed))
+                src = latgen.random_sources(dims, nsrc, gseed + 500)
+                for s in range(nsrc):
+                    x = torch.from_numpy(np.ascontiguousarray(src[s]).reshape(-1)).cuda()
+                    p = nk.nk_sign_params_default(k=k, mu=mu)
+                    al, be, de, info, _ = nk.nk_krylov_basis_device(lat.h, p, x)
+                    kk = info.k_used
+                    a, b, d, lu, _ = nk.nk_inner_matrix(kk, min(lmax, kk), mu == 0.0, al[:kk], be[:kk], de[:kk])
+                    for ell in range(ell_min, lu + 1, ell_step):
+                        mats.append(tridiag_dense(a[:ell], b[:ell], d[:ell]))
+            out.append(mats)
+            count += len(mats)
+        log(f"[rh_train] config {dims} mu={mu}: {count} matrices from {ngauge} gauge fields "
+            f"in {time.time() - t0:.1f} s")
+    return out
+
+
+class Data:
+    """A training set on the device: features, eigenvalues with offsets."""
+
+    def __init__(self, mats, feat, lam_off, lam):
+        self.mats = mats
+        self.feat = feat        # (B, 16) float32 CUDA
+        self.off = lam_off      # (B + 1,) int32 CUDA
+        self.lam = lam          # complex128 CUDA
+        self.n = len(mats)
+
+
+def prepare(mats) -> Data:
+    import torch
+
+    B = len(mats)
+    feat = torch.zeros((B, nk.NK_MLP_IN), dtype=torch.float32, device="cuda")
+    chunk = 256
+    for c0 in range(0, B, chunk):
+        part = mats[c0:c0 + chunk]
+        ld = max(m.shape[0] for m in part)
+        S = np.zeros((len(part), ld, ld), np.complex128)
+        for i, m in enumerate(part):
+            S[i, :m.shape[0], :m.shape[0]] = m
+        fc = torch.zeros((len(part), nk.NK_MLP_IN), dtype=torch.float32, device="cuda")
+        nk.nk_rh_features_device(torch.from_numpy(S).cuda(), [m.shape[0] for m in part], fc)
+        feat[c0:c0 + len(part)] = fc
+    lams = [np.linalg.eigvals(m) for m in mats]
+    off = np.zeros(B + 1, np.int32)
+    off[1:] = np.cumsum([len(x) for x in lams])
+    lam = torch.from_numpy(np.concatenate(lams).astype(np.complex128)).cuda()
+    torch.cuda.synchronize()
+    return Data(mats, feat, torch.from_numpy(off).cuda(), lam)
+
+
+def standardise(params: np.ndarray, data: Data) -> np.ndarray:
+    """Fill the standardisation block from the training features."""
+    f = data.feat.cpu().numpy().astype(np.float64)
+    p = params.copy()
+    mean = f.mean(0)
+    std = f.std(0)
+    p[nk.NK_MLP_NTRAIN:nk.NK_MLP_NTRAIN + nk.NK_MLP_IN] = mean
+    p[nk.NK_MLP_NTRAIN + nk.NK_MLP_IN:] = 1.0 / np.where(std > 1e-6, std, 1.0)
+    return p.astype(np.float32)
+
+
+def loss_of(params_dev, data: Data) -> float:
+    import torch
+
+    y = torch.empty((data.n, nk.NK_MLP_STEPS), dtype=torch.float32, device="cuda")
+    loss = torch.empty(data.n, dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    nk.nk_mlp_forward_device(params_dev, data.feat, y)
+    nk.nk_rh_spectral_loss_device(data.off, data.lam, y, 1.0, loss, dy)
+    return float(loss.mean())
+
+
+def train(params: np.ndarray, data: Data, steps: int = 400, lr: float = 1e-3, batch: int = 0, seed: int = 0,
+          log=None) -> np.ndarray:
+    """Adam on the mean spectral loss, all arithmetic in the library's kernels.
+    batch = 0: full batch; otherwise seeded minibatches of that size."""
+    import torch
+
+    P = torch.from_numpy(np.ascontiguousarray(params, np.float32)).cuda()
+    m = torch.zeros(nk.NK_MLP_NTRAIN, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    grad = torch.zeros_like(m)
+    rng = np.random.default_rng([seed, 3])
+    B = data.n if batch <= 0 else min(batch, data.n)
+    y = torch.empty((B, nk.NK_MLP_STEPS), dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    loss = torch.empty(B, dtype=torch.float32, device="cuda")
+    act = torch.empty((B, 3, nk.NK_MLP_HIDDEN), dtype=torch.float32, device="cuda")
+    delta = torch.empty_like(act)
+    for t in range(1, steps + 1):
+        if B == data.n:
+            feat, off, lam = data.feat, data.off, data.lam
+        else:
+            idx = np.sort(rng.choice(data.n, B, replace=False))
+            feat = data.feat[torch.from_numpy(idx).cuda()].contiguous()
+            offh = data.off.cpu().numpy()
+            lo, hi = offh[idx], offh[idx + 1]
+            sel = np.concatenate([np.arange(a, b) for a, b in zip(lo, hi)])
+            lam = data.lam[torch.from_numpy(sel).cuda()].contiguous()
+            o = np.zeros(B + 1, np.int32)
+            o[1:] = np.cumsum(hi - lo)
+            off = torch.from_numpy(o).cuda()
+        nk.nk_mlp_forward_device(P, feat, y, act)
+        nk.nk_rh_spectral_loss_device(off, lam, y, 1.0 / B, loss, dy)
+        nk.nk_mlp_backward_device(P, feat, act, dy, delta, grad)
+        nk.nk_adam_step_device(nk.NK_MLP_NTRAIN, P, grad, m, v, t, lr)
+        if log and (t == 1 or t % 100 == 0 or t == steps):
+            log(f"[rh_train] step {t}: mean loss {float(loss.mean()):.4f}")
+    torch.cuda.synchronize()
+    return P.cpu().numpy()
+
+
+def rh_iterations(mats, scaling: int, model=None):
+    """Roberts-Higham iteration counts of the library on each matrix."""
+    if scaling == nk.NK_RH_LEARNED:
+        nk.nk_rh_model_set(model)
+    outs, its = [], []
+    try:
+        for c0 in range(0, len(mats), 128):
+            part = mats[c0:c0 + 128]
+            ld = max(m.shape[0] for m in part)
+            S = np.zeros((len(part), ld, ld), np.complex128)
+            for i, m in enumerate(part):
+                S[i, :m.shape[0], :m.shape[0]] = m
+            out, it, _ = nk.nk_rh_sign(S, n=[m.shape[0] for m in part], scaling=scaling)
+            outs += [out[i, :m.shape[0], :m.shape[0]] for i, m in enumerate(part)]
+            its.append(it)
+    finally:
+        if scaling == nk.NK_RH_LEARNED:
+            nk.nk_rh_model_set(None)
+    return outs, np.concatenate(its)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--steps", type=int, default=1500)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--report", default=None, help="write a JSON summary here")
+    args = ap.parse_args(argv)
+    import latgen
+
+    t0 = time.time()
+    groups = collect(seed0=args.seed)
+    # hold out the last gauge field of every configuration
+    tr, hold = [], []
+    gi = 0
+    for cfg in CONFIGS:
+        for g in range(cfg[5]):
+            (hold if g == cfg[5] - 1 else tr).extend(groups[gi])
+            gi += 1
+    print(f"[rh_train] {len(tr)} training and {len(hold)} held-out matrices "
+          f"({time.time() - t0:.1f} s)", flush=True)
+    data = prepare(tr)
+    p0 = standardise(latgen.mlp_init(args.seed), data)
+    import torch
+
+    l0 = loss_of(torch.from_numpy(p0).cuda(), data)
+    p = train(p0, data, steps=args.steps, lr=args.lr, batch=args.batch, seed=args.seed,
+              log=lambda s: print(s, flush=True))
+    l1 = loss_of(torch.from_numpy(p).cuda(), data)
+    np.save(args.out, p.astype(np.float32))
+    summary = {"train": len(tr), "held_out": len(hold), "loss_untrained": l0, "loss_trained": l1}
+    for name, sc, model in (("none", nk.NK_RH_NONE, None), ("det", nk.NK_RH_DET, None),
+                            ("untrained", nk.NK_RH_LEARNED, p0), ("trained", nk.NK_RH_LEARNED, p)):
+        _, it = rh_iterations(hold, sc, model)
+        summary[f"iters_{name}"] = float(np.mean(it))
+    summary["seconds"] = time.time() - t0
+    print(json.dumps(summary), flush=True)
+    if args.report:
+        with open(args.report, "w") as fh:
+            json.dump(summary, fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
