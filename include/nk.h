@@ -102,7 +102,10 @@ typedef struct nk_sign_params {
   int32_t profile;     /* n > 0: time the two outer-recurrence kernels of every n-th step with HIP
                         * events bound to those launches on the caller's stream (0 = off;
                         * negative = NK_EINVAL) */
-  int32_t reserved;
+  int32_t block;       /* 1: run the nrhs sources in lockstep (two-sided Lanczos with FP64 and
+                        * tol = 0: one stencil kernel per step loads each link once for all
+                        * sources; batched small problems); other cases, and 0, run the sources
+                        * one after another */
 } nk_sign_params;
 
 typedef struct nk_sign_info {
@@ -123,7 +126,7 @@ typedef struct nk_sign_info {
 
 /* Fill *p with defaults: m_w = -1, mu = 0, k = 100, ell = 0, tol = 0, nrhs = 1,
  * FP64, unscaled RH, two_pass AUTO, est_delay = 0, check_every = 50,
- * rh_maxit = 100, rh_tol = 1e-13, ell_per_rhs = NULL, profile = 0. */
+ * rh_maxit = 100, rh_tol = 1e-13, ell_per_rhs = NULL, profile = 0, block = 0. */
 void nk_sign_params_default(nk_sign_params* p);
 
 /* Create a lattice context on the current HIP device.  dims = {Lx, Ly, Lz, Lt},
@@ -242,6 +245,13 @@ int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, dou
  * early-stop checks and the small problem need host decisions). */
 int nk_sign_apply_device(nk_lattice* lat, const nk_sign_params* p, const void* x, void* y,
                          nk_sign_info* info, nk_stream_t stream);
+
+/* Direction groups (2 or 4) of the outer-recurrence stencil kernel that the
+ * autotuner chose on this handle for the given precision and recurrence
+ * (hermitian != 0: Lanczos), 0 before the first basis run; NK_EINVAL for a
+ * NULL handle or an unknown precision.  The autotuner times both kernels once
+ * per handle on the first outer-basis run and keeps the faster. */
+int nk_stencil_groups(nk_lattice* lat, int32_t precision, int32_t hermitian);
 
 /* Thread-local message for the last failure ("" if none). */
 const char* nk_last_error(void);

@@ -95,7 +95,7 @@ static int validate_params(nk_lattice* lat, const nk_sign_params* p) {
   }
   if (p->k < 1 || p->ell < 0 || p->nrhs < 1 || p->precision < 0 || p->precision > 2 || p->rh_maxit < 1 ||
       p->est_delay < 0 || p->est_delay >= p->k || !(p->tol >= 0.0) || p->two_pass < 0 || p->two_pass > 2 ||
-      p->rh_scaling < 0 || p->rh_scaling > 2 || p->profile < 0 || !std::isfinite(p->mu) || !std::isfinite(p->m_w)) {
+      p->rh_scaling < 0 || p->rh_scaling > 2 || p->profile < 0 || p->block < 0 || p->block > 1 || !std::isfinite(p->mu) || !std::isfinite(p->m_w)) {
     set_error("invalid sign parameters (k=%d ell=%d nrhs=%d precision=%d est_delay=%d)", p->k, p->ell, p->nrhs,
               p->precision, p->est_delay);
     return NK_EINVAL;
@@ -533,6 +533,14 @@ int nk_inner_matrix(int32_t k, int32_t ell, int32_t hermitian, const double* alp
   return e;
 }
 
+int nk_stencil_groups(nk_lattice* lat, int32_t precision, int32_t hermitian) {
+  if (!lat || precision < 0 || precision > 2) {
+    set_error("invalid argument to nk_stencil_groups");
+    return NK_EINVAL;
+  }
+  return lat->k1_groups[hermitian ? 1 : 0][precision];
+}
+
 int nk_rh_model_set(const float* params) { return nk::mlp_model_set(params); }
 
 int nk_rh_features_device(int32_t batch, int32_t ld, const int32_t* n, const void* S, float* feat,
@@ -624,13 +632,20 @@ int nk_sign_apply_device(nk_lattice* lat, const nk_sign_params* p, const void* x
     info->est = std::numeric_limits<double>::quiet_NaN();
   }
   const size_t n = (size_t)12 * lat->g.V;
-  int worst = NK_OK;
   for (int r = 0; r < p->nrhs; ++r) {
     const int ell = p->ell_per_rhs ? p->ell_per_rhs[r] : p->ell;
     if (ell < 0 || ell > p->k) {
       set_error("ell_per_rhs[%d] = %d outside [0, k]", r, ell);
       return NK_EINVAL;
     }
+  }
+  if (p->block && p->nrhs > 1) {
+    const int e = block_sign(lat, p, (const C64*)x, (C64*)y, info, (hipStream_t)stream);
+    if (e != 1) return e;  // 1: not a case the block path covers; run the sources one after another
+  }
+  int worst = NK_OK;
+  for (int r = 0; r < p->nrhs; ++r) {
+    const int ell = p->ell_per_rhs ? p->ell_per_rhs[r] : p->ell;
     int e = sign_one(lat, p, ell, (const C64*)x + r * n, (C64*)y + r * n, info, (hipStream_t)stream);
     if (e < 0) return e;
     if (e > worst) worst = e;

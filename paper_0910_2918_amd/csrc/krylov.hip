@@ -20,6 +20,10 @@ namespace nk {
 
 constexpr int NT = 256;
 
+#ifndef NK_AUTOTUNE
+#define NK_AUTOTUNE 1  // choose the direction groups of K1 by timing both on first use
+#endif
+
 template <int NQ>
 __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
   __shared__ double sh[NQ][NT / 64];
@@ -485,16 +489,105 @@ int prof_collect(nk_lattice* lat, double* t_k1, double* t_k2, int* n_k1, int* n_
   return NK_OK;
 }
 
+// K1 workgroups for NG direction groups: NT / 64 / NG blocks of 64 sites
+// (Lanczos, one lane per site) or of 32 sites (two-sided, two lanes per site)
+static int k1_blocks(const Geom& g, int hermitian, int ng) {
+  const int spb = (hermitian ? 64 : 32) * ((NT / 64) / ng);
+  return (g.V + spb - 1) / spb;
+}
+
+// one K1 launch with NG = ng direction groups
+template <class R, class LK>
+static void launch_k1(int ng, const Geom& g, const BasisPlan& bp, const LK& lk, R diag, int j, const Cx<R>* vj,
+                      const Cx<R>* wj, const Cx<R>* vjm1, const Cx<R>* wjm1, Cx<R>* p, Cx<R>* q,
+                      const double* partIn, int nbIn, double* partOut, Coefs c, hipEvent_t e0, hipEvent_t e1,
+                      hipStream_t st) {
+  const int nb1 = k1_blocks(g, bp.hermitian, ng);
+  const R eft = (R)exp(bp.mu), ebt = (R)exp(-bp.mu);
+  if (bp.hermitian) {
+    if (ng == 2)
+      hipExtLaunchKernelGGL((k_lan1<R, LK, 2>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, j, vj, vjm1, p,
+                            partIn, nbIn, partOut, c);
+    else
+      hipExtLaunchKernelGGL((k_lan1<R, LK, 4>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, j, vj, vjm1, p,
+                            partIn, nbIn, partOut, c);
+  } else {
+    if (ng == 2)
+      hipExtLaunchKernelGGL((k_bil1<R, LK, 2>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j, vj,
+                            wj, vjm1, wjm1, p, q, partIn, nbIn, partOut, c);
+    else
+      hipExtLaunchKernelGGL((k_bil1<R, LK, 4>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j, vj,
+                            wj, vjm1, wjm1, p, q, partIn, nbIn, partOut, c);
+  }
+}
+
+// The autotuner: time K1 with 2 and with 4 direction groups on this lattice,
+// precision and recurrence (ten launches of each after two warm-up launches,
+// on scratch coefficients and valid partial sums) and keep the faster.  The
+// choice is made once per handle and reused by every later run, so a
+// second (two-pass) sweep runs the same kernels as the first.
+template <class R, class LK>
+static int tune_k1(nk_lattice* lat, const BasisPlan& bp, const LK& lk, BasisBuffers& b, hipStream_t st, int* ng_out) {
+  const Geom& g = lat->g;
+  const int nb2 = nb_elem(g);
+  if (lat->tunebuf.ensure(4096)) return NK_ENOMEM;
+  char* tb = lat->tunebuf.as<char>();
+  Coefs c;
+  c.alpha = (C64*)(tb);
+  c.beta = (C64*)(tb + 256);
+  c.delta = (C64*)(tb + 512);
+  c.sv = (double*)(tb + 768);
+  c.sw = (C64*)(tb + 1024);
+  c.flags = (int*)(tb + 1280);
+  std::vector<double> parts((size_t)4 * nb2, 1.0 / nb2);  // s = 1 + i, |v|^2 = |w|^2 = 1: no breakdown
+  std::vector<char> zeros(2048, 0);
+  NK_HIP(hipMemcpyAsync(tb, zeros.data(), zeros.size(), hipMemcpyHostToDevice, st));
+  NK_HIP(hipMemcpyAsync(b.partB, parts.data(), parts.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  const R diag = (R)(4.0 + bp.m_w);
+  auto colp = [&](int s) { return reinterpret_cast<Cx<R>*>(b.vk + (size_t)s * b.colbytes); };
+  Cx<R>* w0 = reinterpret_cast<Cx<R>*>(b.wring);
+  Cx<R>* w1 = reinterpret_cast<Cx<R>*>(b.wring + b.colbytes);
+  hipEvent_t ev[2];
+  NK_HIP(hipEventCreate(&ev[0]));
+  NK_HIP(hipEventCreate(&ev[1]));
+  float best = INFINITY;
+  int best_ng = NK_GROUPS;
+  for (int ng : {4, 2}) {
+    for (int rep = 0; rep < 12; ++rep) {
+      if (rep == 2) NK_HIP(hipEventRecord(ev[0], st));
+      launch_k1<R, LK>(ng, g, bp, lk, diag, 1, colp(1), w1, colp(0), w0, reinterpret_cast<Cx<R>*>(b.p),
+                       reinterpret_cast<Cx<R>*>(b.q), b.partB, nb2, b.partA, c, nullptr, nullptr, st);
+    }
+    NK_HIP(hipGetLastError());
+    NK_HIP(hipEventRecord(ev[1], st));
+    NK_HIP(hipEventSynchronize(ev[1]));
+    float ms = 0.f;
+    NK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    if (ms < best) {
+      best = ms;
+      best_ng = ng;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  *ng_out = best_ng;
+  return NK_OK;
+}
+
 template <class R, class LK>
 static int run_steps(nk_lattice* lat, const BasisPlan& bp, const LK& lk, const C64* x, int j0, int j1, Coefs c,
                      BasisBuffers& b, LiftAcc lift, hipStream_t st) {
   const Geom& g = lat->g;
   const int n = 12 * g.V;
-  constexpr int NG = NK_GROUPS;
-  // K1 workgroups: NT / 64 / NG blocks of 64 sites (Lanczos, one lane per
-  // site) or of 32 sites (two-sided, two lanes per site)
-  const int spb = (bp.hermitian ? 64 : 32) * ((NT / 64) / NG);
-  const int nb1 = (g.V + spb - 1) / spb, nb2 = nb_elem(g);
+  int& ng = lat->k1_groups[bp.hermitian ? 1 : 0][bp.prec];
+  if (ng == 0) {  // first run on this handle: before k_start, whose partial sums the tuning overwrites
+    if (NK_AUTOTUNE && j0 == 0) {
+      if (int e = tune_k1<R, LK>(lat, bp, lk, b, st, &ng)) return e;
+    } else {
+      ng = NK_GROUPS;
+    }
+  }
+  const int nb1 = k1_blocks(g, bp.hermitian, ng), nb2 = nb_elem(g);
   const R diag = (R)(4.0 + bp.m_w);
   auto col = [&](int j) -> Cx<R>* {
     const int s = bp.store ? j : (j % 3);
@@ -522,22 +615,16 @@ static int run_steps(nk_lattice* lat, const BasisPlan& bp, const LK& lk, const C
         if (int r = prof_event(lat, &e0)) return r;
         if (int r = prof_event(lat, &e1)) return r;
       }
-      if (bp.hermitian) {
-        if (kind == 0)
-          hipExtLaunchKernelGGL((k_lan1<R, LK, NG>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, j, col(j),
-                                j > 0 ? col(j - 1) : col(j), p, b.partB, nb2, b.partA, c);
-        else
-          hipExtLaunchKernelGGL((k_lan2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, col(j), col(j + 1),
-                                b.partA, nb1, b.partB, c, lift);
+      if (kind == 0) {
+        launch_k1<R, LK>(ng, g, bp, lk, diag, j, col(j), bp.hermitian ? nullptr : wsl(j), j > 0 ? col(j - 1) : col(j),
+                         bp.hermitian ? nullptr : (j > 0 ? wsl(j - 1) : wsl(j)), p, q, b.partB, nb2, b.partA, c, e0,
+                         e1, st);
+      } else if (bp.hermitian) {
+        hipExtLaunchKernelGGL((k_lan2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, col(j), col(j + 1),
+                              b.partA, nb1, b.partB, c, lift);
       } else {
-        const R eft = (R)exp(bp.mu), ebt = (R)exp(-bp.mu);
-        if (kind == 0)
-          hipExtLaunchKernelGGL((k_bil1<R, LK, NG>), dim3(nb1), dim3(NT), 0, st, e0, e1, 0, g, lk, diag, eft, ebt, j,
-                                col(j), wsl(j), j > 0 ? col(j - 1) : col(j), j > 0 ? wsl(j - 1) : wsl(j), p, q,
-                                b.partB, nb2, b.partA, c);
-        else
-          hipExtLaunchKernelGGL((k_bil2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, q, col(j), wsl(j),
-                                col(j + 1), wsl(j + 1), b.partA, nb1, b.partB, c, lift);
+        hipExtLaunchKernelGGL((k_bil2<R>), dim3(nb2), dim3(NT), 0, st, e0, e1, 0, n, j, p, q, col(j), wsl(j),
+                              col(j + 1), wsl(j + 1), b.partA, nb1, b.partB, c, lift);
       }
       NK_HIP(hipGetLastError());
       if (timed) lat->evkind.push_back(kind);
@@ -583,6 +670,16 @@ int lift_run(nk_lattice* lat, const BasisPlan& bp, int kused, const C64* z, doub
   else
     hipLaunchKernelGGL(k_lift<float>, dim3((n + NT - 1) / NT), dim3(NT), 0, st, n, kused, (const C32*)vk,
                        colstride, lc, y_dev);
+  NK_HIP(hipGetLastError());
+  return NK_OK;
+}
+
+// y = ||x|| sum_j z_j v_j over kused FP64 columns vk + j * colstride (lc: workspace [kused])
+int lift_columns(int n, int kused, const C64* vk, size_t colstride, const C64* z, const double* sv, C64* lc, C64* y,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_lift_coef, dim3((kused + 255) / 256), dim3(256), 0, st, kused, z, sv, lc);
+  hipLaunchKernelGGL(k_lift<double>, dim3((n + NT - 1) / NT), dim3(NT), 0, st, n, kused, vk, colstride,
+                     (const C64*)lc, y);
   NK_HIP(hipGetLastError());
   return NK_OK;
 }

@@ -133,6 +133,12 @@ struct nk_lattice {
   nk::DevBuf canon;    // canonical-layout staging for host calls
   nk::DevBuf lift;     // lift coefficients
   nk::DevBuf tmp;      // device-layout temporaries of the stand-alone operator calls
+  nk::DevBuf bvec;     // multi-source path: per-source vectors (basis, W ring, p, q, x, y)
+  nk::DevBuf bsmall;   // multi-source path: coefficients, partial sums, small problems
+  // autotuned direction groups of the outer-recurrence stencil kernel,
+  // [hermitian][precision]; 0 = not tuned yet
+  int k1_groups[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  nk::DevBuf tunebuf;  // scratch coefficients of the autotuner
   // optional per-launch timing of the outer-recurrence kernels
   std::vector<hipEvent_t> evpool;
   std::vector<int> evkind;  // kind of each recorded (start, stop) pair: 0 = K1, 1 = K2
@@ -183,12 +189,22 @@ int lift_run(nk_lattice* lat, const BasisPlan& bp, int kused, const C64* z, doub
 int two_pass_lift(nk_lattice* lat, const BasisPlan& bp, const C64* x_canon, int kused, const C64* z, Coefs c,
                   C64* y_canon, hipStream_t st);
 
+int lift_columns(int n, int kused, const C64* vk, size_t colstride, const C64* z, const double* sv, C64* lc, C64* y,
+                 hipStream_t st);
+
+// block.hip -- many sources in lockstep (two-sided Lanczos, FP64); returns 1
+// when the request is not one the block path covers (the caller then runs
+// the sources one after another)
+int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64* y_canon, nk_sign_info* info,
+               hipStream_t st);
+
 // small.hip -- the small problem on the device
 struct SmallOut {
   int rh_iters = 0;
   int ell_used = 0;
   double rh_residual = 0;
   C64* hl_host = nullptr;  // if set: receives H_ell's diagonal, super- and sub-diagonal (3 x ell, host)
+  C64* vl_dev = nullptr;   // if set: receives the inner basis V_ell (device, column j at j * k)
   bool inner_only = false; // stop after the inner projection (no Roberts-Higham, no lift)
 };
 int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,

@@ -529,6 +529,8 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     NK_HIP(hipMemcpyAsync(out->hl_host + 2 * lu, s.d, lu * sizeof(C64), hipMemcpyDeviceToHost, st));
     NK_HIP(hipStreamSynchronize(st));
   }
+  if (out && out->vl_dev)
+    NK_HIP(hipMemcpyAsync(out->vl_dev, s.V, (size_t)k * lu * sizeof(C64), hipMemcpyDeviceToDevice, st));
   if (out && out->inner_only) {
     out->ell_used = lu;
     return fl[0] ? NK_WARN_BREAKDOWN : NK_OK;

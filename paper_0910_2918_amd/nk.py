@@ -64,6 +64,7 @@ EXPORTS = (
     "nk_adam_step_device",
     "nk_sign_apply",
     "nk_sign_apply_device",
+    "nk_stencil_groups",
     "nk_last_error",
     "nk_version",
 )
@@ -96,7 +97,7 @@ class nk_sign_params(C.Structure):
         ("rh_tol", C.c_double),
         ("ell_per_rhs", C.POINTER(C.c_int32)),
         ("profile", C.c_int32),
-        ("reserved", C.c_int32),
+        ("block", C.c_int32),
     ]
 
 
@@ -161,6 +162,7 @@ def library():
         "nk_adam_step_device": (C.c_int, [i32, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
         "nk_sign_apply": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info)]),
         "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
+        "nk_stencil_groups": (C.c_int, [vp, i32, i32]),
         "nk_last_error": (C.c_char_p, []),
         "nk_version": (C.c_char_p, []),
     }
@@ -199,6 +201,11 @@ def _hptr(a: np.ndarray):
     if a.dtype != np.complex128 or not a.flags["C_CONTIGUOUS"]:
         raise ValueError("expected a C-contiguous complex128 array")
     return C.c_void_p(a.ctypes.data)
+
+
+def nk_stencil_groups(h, precision: int = 0, hermitian: bool = False) -> int:
+    """Direction groups the autotuner chose for the stencil kernel (0 = not yet tuned)."""
+    return _check(library().nk_stencil_groups(h, int(precision), 1 if hermitian else 0))
 
 
 def nk_last_error() -> str:

@@ -1,0 +1,117 @@
+"""Many sources in lockstep (nk_sign_params.block = 1), through the C ABI.
+
+Against the oracle's nested / non-nested run of each source at the same
+(k, ell) (method level, <= max(1e-10, 10 eps_true(k))), against the
+one-at-a-time path, and across the one-pass and two-pass lifts.
+"""
+import numpy as np
+import pytest
+
+import latgen
+from oracle import nested as N
+from oracle import wilson as W
+from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (4, 4, 2, 6)
+MU = 0.3
+
+
+@pytest.fixture(scope="module")
+def setup():
+    lat, u = make_lattice(DIMS, 0.6, seed=1)
+    xs = latgen.random_sources(DIMS, 4, 7)
+    yield lat, u, xs
+    lat.close()
+
+
+def _run(lat, xs, **kw):
+    b = nk()
+    p = b.nk_sign_params_default(mu=MU, nrhs=len(xs), **kw)
+    dx = to_dev(xs)
+    dy = torch_cuda().empty_like(dx)
+    info, rc = b.nk_sign_apply_device(lat.h, p, dx, dy)
+    return to_host(dy).reshape(len(xs), -1), info, rc
+
+
+@pytest.mark.parametrize("ells", [[20, 45, 80, 33], [0, 0, 0, 0]])
+def test_block_matches_oracle(setup, ells):
+    lat, u, xs = setup
+    k = 160
+    banner(f"block {DIMS} mu={MU} r=4 k={k} ells={ells}")
+    y, info, rc = _run(lat, xs, k=k, ell_per_rhs=ells, block=1)
+    assert rc == 0
+    f = lambda v: W.a_apply(u, v.reshape(xs[0].shape), M_W, MU).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(xs[0].shape), M_W, -MU).reshape(-1)
+    for s in range(4):
+        yo, _ = N.sign_apply(f, fd, xs[s], k, ells[s], False)
+        yref, _ = N.sign_apply(f, fd, xs[s], 500, 0, False)
+        eps_true = rel(yo, yref)
+        assert rel(y[s], yo) <= max(1e-10, 10 * eps_true), (s, rel(y[s], yo), eps_true)
+
+
+def test_block_matches_one_at_a_time(setup):
+    """Same method, other reduction order: the two agree to rounding that the
+    recurrence amplifies over k steps, far below the truncation error."""
+    lat, u, xs = setup
+    ells = [30, 60, 90, 45]
+    banner("block vs one-at-a-time, r=4 k=160")
+    yb, _, _ = _run(lat, xs, k=160, ell_per_rhs=ells, block=1)
+    ys, _, _ = _run(lat, xs, k=160, ell_per_rhs=ells, block=0)
+    for s in range(4):
+        assert rel(yb[s], ys[s]) < 1e-9
+
+
+def test_block_two_pass_matches_one_pass(setup):
+    lat, u, xs = setup
+    ells = [25, 50, 75, 100]
+    banner("block two-pass vs one-pass")
+    y1, i1, _ = _run(lat, xs, k=150, ell_per_rhs=ells, block=1, two_pass=2)
+    y2, i2, _ = _run(lat, xs, k=150, ell_per_rhs=ells, block=1, two_pass=1)
+    assert i1.two_pass == 0 and i2.two_pass == 1
+    for s in range(4):
+        assert rel(y2[s], y1[s]) < 1e-13
+
+
+def test_block_rejects_mixed_nesting(setup):
+    lat, u, xs = setup
+    b = nk()
+    banner("block with nested and non-nested sources")
+    with pytest.raises(b.NKError) as ei:
+        _run(lat, xs, k=60, ell_per_rhs=[0, 20, 20, 20], block=1)
+    assert ei.value.code == b.NK_EINVAL
+
+
+def test_block_mu0_runs_one_at_a_time(setup):
+    """mu = 0 (Lanczos) is not a lockstep case: the sources run one after
+    another, bit-identical to block = 0."""
+    lat, u, xs = setup
+    b = nk()
+    banner("block request at mu = 0")
+    p0 = b.nk_sign_params_default(mu=0.0, nrhs=2, k=80, ell=30, block=1)
+    p1 = b.nk_sign_params_default(mu=0.0, nrhs=2, k=80, ell=30, block=0)
+    dx = to_dev(xs[:2])
+    d0 = torch_cuda().empty_like(dx)
+    d1 = torch_cuda().empty_like(dx)
+    b.nk_sign_apply_device(lat.h, p0, dx, d0)
+    b.nk_sign_apply_device(lat.h, p1, dx, d1)
+    assert np.array_equal(to_host(d0), to_host(d1))
+
+
+def test_block_8x4_sixteen_sources_uneven_ell():
+    """16 sources with uneven ell at 8^4 mu = 0.3 against the one-at-a-time
+    path, at the method level (the truth: non-nested k = 600)."""
+    dims = (8, 8, 8, 8)
+    lat, u = make_lattice(dims, 0.6, seed=2)
+    xs = latgen.random_sources(dims, 16, 9)
+    ells = latgen.uneven_ell(16, 40, 120, 1).tolist()
+    banner(f"block 8^4 r=16 k=300 ells={ells}")
+    yb, _, rc = _run(lat, xs, k=300, ell_per_rhs=ells, block=1)
+    assert rc == 0
+    ys, _, _ = _run(lat, xs, k=300, ell_per_rhs=ells, block=0)
+    yt, _, _ = _run(lat, xs, k=600, ell=0, block=1)
+    for s in range(16):
+        eps_true = rel(ys[s], yt[s])
+        assert rel(yb[s], ys[s]) <= max(1e-10, 10 * eps_true), (s, rel(yb[s], ys[s]), eps_true)
+    lat.close()
