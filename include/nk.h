@@ -102,10 +102,11 @@ typedef struct nk_sign_params {
   int32_t profile;     /* n > 0: time the two outer-recurrence kernels of every n-th step with HIP
                         * events bound to those launches on the caller's stream (0 = off;
                         * negative = NK_EINVAL) */
-  int32_t block;       /* 1: run the nrhs sources in lockstep (two-sided Lanczos with FP64 and
-                        * tol = 0: one stencil kernel per step loads each link once for all
-                        * sources; batched small problems); other cases, and 0, run the sources
-                        * one after another */
+  int32_t block;       /* 1: run the nrhs sources in lockstep (two-sided Lanczos, FP64, tol = 0):
+                        * four launches per step for all sources, batched small problems;
+                        * 2: the same with each sweep of the basis replayed from a HIP graph
+                        * captured on first use and cached on the handle; other cases, and 0,
+                        * run the sources one after another */
 } nk_sign_params;
 
 typedef struct nk_sign_info {

@@ -95,7 +95,7 @@ static int validate_params(nk_lattice* lat, const nk_sign_params* p) {
   }
   if (p->k < 1 || p->ell < 0 || p->nrhs < 1 || p->precision < 0 || p->precision > 2 || p->rh_maxit < 1 ||
       p->est_delay < 0 || p->est_delay >= p->k || !(p->tol >= 0.0) || p->two_pass < 0 || p->two_pass > 2 ||
-      p->rh_scaling < 0 || p->rh_scaling > 2 || p->profile < 0 || p->block < 0 || p->block > 1 || !std::isfinite(p->mu) || !std::isfinite(p->m_w)) {
+      p->rh_scaling < 0 || p->rh_scaling > 2 || p->profile < 0 || p->block < 0 || p->block > 2 || !std::isfinite(p->mu) || !std::isfinite(p->m_w)) {
     set_error("invalid sign parameters (k=%d ell=%d nrhs=%d precision=%d est_delay=%d)", p->k, p->ell, p->nrhs,
               p->precision, p->est_delay);
     return NK_EINVAL;
@@ -275,6 +275,9 @@ static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64
 }  // namespace nk
 
 nk_lattice::~nk_lattice() {
+  for (auto& gr : graphs)
+    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   U64.release();
   U32.release();
   Ubf.release();

@@ -1,20 +1,22 @@
 // Many sources in lockstep: the outer two-sided Lanczos basis of Sec. 2 for
 // r sources at once, the small problems of Eqs. (3)-(6) batched, and the lift.
 //
-// Each source keeps its own recurrence and coefficients; what they share is
-// the gauge field.  The stencil kernel (k_blk1) gives every wave of a
-// workgroup one direction of 32 sites, loads that direction's two links
-// into registers once, and then applies them to all r sources in turn, so
-// the links cost 576 bytes per site per step for all sources together
-// instead of per source.  A step is four launches for all sources:
+// Each source keeps its own recurrence and coefficients.  A step is four
+// launches for all sources together:
 //   k_blk1  A v_j, A^dag w_j minus the previous vectors, partial w~^dag A v~
+//           (grid: site blocks x sources)
 //   k_bred1 alpha_j per source (fixed-order reduction)
 //   k_blk2  v_hat, w_hat (new unnormalised columns), partial s, |v|^2, |w|^2
 //   k_bred2 delta, beta, the scales and the breakdown test per source
-// Every reduction is deterministic, so a second sweep over the same data
-// (two-pass lift) reproduces the first bit for bit.  The small problems run
-// as one inner projection per source followed by one batched
-// Roberts-Higham call over the uneven ell of all sources.
+// so launches and reductions are shared by the sources, and the small
+// problems run as one inner projection per source followed by one batched
+// Roberts-Higham call over the uneven ell of all sources.  The links are
+// read once per source: on MI355X they stay in the 256 MB Infinity Cache
+// between sources (38 MB at 16^4, 75 MB at 16^3 x 32), so re-reading them
+// costs no HBM traffic, while keeping them in registers for all sources
+// would cut the occupancy of the stencil kernel in half.  Every reduction
+// is deterministic, so a second sweep over the same data (two-pass lift)
+// reproduces the first bit for bit.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -149,106 +151,73 @@ __global__ void __launch_bounds__(BT) k_bred1(BArgs a, int j) {
   a.alpha[(size_t)s * a.k + j] = cmul(conj(swj), svj * mk(red[0], red[1]));
 }
 
-// both hops of direction NU with the links in registers
-template <int NU>
-__device__ __forceinline__ void dir_hops(const Cx<double> (&uf)[9], const Cx<double> (&ub)[9], const C64* in, int V,
-                                         int sf, int sb, double cf, double cb, C64 (&acc)[12]) {
-  hop_with<NU, true>(uf, in, V, sf, cf, acc);
-  hop_fence();
-  hop_with<NU, false>(ub, in, V, sb, cb, acc);
-}
-
-// the stencil step of every running source: p = A v_j - beta_j v_{j-1},
+// the stencil step of source blockIdx.y: p = A v_j - beta_j v_{j-1},
 // q = A^dag w_j - delta_j w_{j-1} (both scaled by the lazy normalisation),
-// partial w~_j^dag (A v~_j).  Four waves = four directions of 32 sites, two
-// lanes per site (even: A v, odd: A^dag w).
+// partial w~_j^dag (A v~_j).  The body of the one-source kernel: directions
+// split over the waves (hop_group), two lanes per site.  Workgroups run
+// source by source, so each source keeps the one-source kernel's locality;
+// the links, read once per source, stay in the Infinity Cache between
+// sources.
+template <int NG>
 __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, double diag, double eft, double ebt,
                                               int j, BArgs a) {
-  constexpr int NG = 4, M = 3;
+  constexpr int M = 12 / NG;
+  constexpr int NSB = (BT / 64) / NG;
   __shared__ XBuf<double, NG> xb;
+  const int src = blockIdx.y;
+  if (a.flags[src]) return;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gi = w;  // direction of this wave
-  const int f = lane & 1;
-  const int s = xcd_block() * 32 + (lane >> 1);
+  const int gi = w % NG, sb = w / NG;
+  const int f = lane & 1;  // 0: A v_j, 1: A^dag w_j
+  const C64* in = f ? colw(a, src, j) : colv(a, src, j);
+  const int s = (xcd_block() * NSB + sb) * 32 + (lane >> 1);
   const bool live = s < g.V;
-  const int sh = live ? s : 0;
-  const SiteC x = site_coords(g, sh);
-  Cx<double> uf[9], ub[9];
-  int sf, sb;
-  double wf, wb;
-  if (gi == 0)
-    hop_setup<0>(g, sh, x, lk, uf, ub, sf, sb, wf, wb);
-  else if (gi == 1)
-    hop_setup<1>(g, sh, x, lk, uf, ub, sf, sb, wf, wb);
-  else if (gi == 2)
-    hop_setup<2>(g, sh, x, lk, uf, ub, sf, sb, wf, wb);
-  else
-    hop_setup<3>(g, sh, x, lk, uf, ub, sf, sb, wf, wb);
-  // temporal factors: A(mu) on v, A(-mu) = A(mu)^dag on w
-  const double cf = gi == 3 ? wf * (f ? ebt : eft) : wf;
-  const double cb = gi == 3 ? wb * (f ? eft : ebt) : wb;
-  for (int src = 0; src < a.r; ++src) {
-    if (a.flags[src]) continue;  // the same in every thread
-    const C64* in = f ? colw(a, src, j) : colv(a, src, j);
-    C64 mine[M];
-    {
-      C64 acc[12];
+  C64 mine[M];
+  {
+    C64 acc[1][12];
+    hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, acc);  // dead lanes hop at site 0
+    xput<NG>(xb, w, gi, lane, acc, mine);
+  }
+  __syncthreads();
+  const size_t kk = (size_t)src * (a.k + 1);
+  const double svj = a.sv[kk + j];
+  const C64 swj = a.sw[kk + j];
+  C64 scale = f ? swj : mk(svj, 0.0), sub = mk(0.0, 0.0);
+  if (j > 0) {
+    const C64 bm = a.beta[(size_t)src * a.k + j - 1], dm = a.delta[(size_t)src * a.k + j - 1];
+    sub = f ? cmul(dm, a.sw[kk + j - 1]) : a.sv[kk + j - 1] * bm;
+  }
+  const C64* prev = f ? colw(a, src, j > 0 ? j - 1 : 0) : colv(a, src, j > 0 ? j - 1 : 0);
+  C64* out = f ? vq(a, src) : vp(a, src);
+  const C64* wj = colw(a, src, j);
+  double dre = 0.0, dim = 0.0;
+  if (live) {
+    int se = s;
+    asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
 #pragma unroll
-      for (int c = 0; c < 12; ++c) acc[c] = mk(0.0, 0.0);
-      if (gi == 0)
-        dir_hops<0>(uf, ub, in, g.V, sf, sb, cf, cb, acc);
-      else if (gi == 1)
-        dir_hops<1>(uf, ub, in, g.V, sf, sb, cf, cb, acc);
-      else if (gi == 2)
-        dir_hops<2>(uf, ub, in, g.V, sf, sb, cf, cb, acc);
-      else
-        dir_hops<3>(uf, ub, in, g.V, sf, sb, cf, cb, acc);
-      C64 a1[1][12];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) a1[0][c] = acc[c];
-      xput<NG>(xb, w, gi, lane, a1, mine);
-    }
-    __syncthreads();
-    const size_t kk = (size_t)src * (a.k + 1);
-    const double svj = a.sv[kk + j];
-    const C64 swj = a.sw[kk + j];
-    C64 scale = f ? swj : mk(svj, 0.0), sub = mk(0.0, 0.0);
-    if (j > 0) {
-      const C64 bm = a.beta[(size_t)src * a.k + j - 1], dm = a.delta[(size_t)src * a.k + j - 1];
-      sub = f ? cmul(dm, a.sw[kk + j - 1]) : a.sv[kk + j - 1] * bm;
-    }
-    const C64* prev = f ? colw(a, src, j > 0 ? j - 1 : 0) : colv(a, src, j > 0 ? j - 1 : 0);
-    C64* out = f ? vq(a, src) : vp(a, src);
-    const C64* wj = colw(a, src, j);
-    double dre = 0.0, dim = 0.0;
-    if (live) {
-      int se = s;
-      asm volatile("" : "+v"(se));
-#pragma unroll
-      for (int cl = 0; cl < M; ++cl) {
-        const int cc = gi * M + cl;
-        const C64 hs = xsum<NG>(xb, 0, gi, lane, cl, mine[cl]);
-        const size_t i = (size_t)cc * g.V + se;
-        C64 av = diag * in[i] - 0.5 * hs;
-        if (cc >= 6) av = mk(-av.re, -av.im);
-        C64 o = cmul(scale, av);
-        if (j > 0) o = o - cmul(sub, prev[i]);
-        out[i] = o;
-        if (f == 0) {
-          const C64 t = cmulc(wj[i], av);
-          dre += t.re;
-          dim += t.im;
-        }
+    for (int cl = 0; cl < M; ++cl) {
+      const int cc = gi * M + cl;
+      const C64 hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
+      const size_t i = (size_t)cc * g.V + se;
+      C64 av = diag * in[i] - 0.5 * hs;
+      if (cc >= 6) av = mk(-av.re, -av.im);
+      C64 o = cmul(scale, av);
+      if (j > 0) o = o - cmul(sub, prev[i]);
+      out[i] = o;
+      if (f == 0) {
+        const C64 t = cmulc(wj[i], av);
+        dre += t.re;
+        dim += t.im;
       }
     }
-    double v[2] = {dre, dim};
-    bsum<2>(v);  // its barriers also order this source's exchange reads before the next one's writes
-    if (threadIdx.x == 0) {
-      double* p1 = a.part1 + (size_t)src * 2 * a.nb1;
-      p1[blockIdx.x] = v[0];
-      p1[a.nb1 + blockIdx.x] = v[1];
-    }
+  }
+  double v[2] = {dre, dim};
+  bsum<2>(v);
+  if (threadIdx.x == 0) {
+    double* p1 = a.part1 + (size_t)src * 2 * a.nb1;
+    p1[blockIdx.x] = v[0];
+    p1[a.nb1 + blockIdx.x] = v[1];
   }
 }
 
@@ -273,17 +242,37 @@ __global__ void __launch_bounds__(BT) k_blk2(BArgs a, int j) {
   const bool lift = a.lc != nullptr && j + 1 < a.kused[s];
   const C64 lcn = lift ? a.lc[(size_t)s * a.k + j + 1] : mk(0.0, 0.0);
   double sre = 0.0, sim = 0.0, nv = 0.0, nw = 0.0;
-  for (size_t i = (size_t)blockIdx.x * BT + threadIdx.x; i < a.n; i += (size_t)gridDim.x * BT) {
-    const C64 vr = p[i] - cmul(av, v[i]);
-    const C64 wr = q[i] - cmul(aw, w[i]);
-    vn[i] = vr;
-    wn[i] = wr;
-    const C64 t = cmulc(wr, vr);
-    sre += t.re;
-    sim += t.im;
-    nv += norm2(vr);
-    nw += norm2(wr);
-    if (lift) y[i] = y[i] + cmul(lcn, vr);
+  // four elements per thread and batch, all loads before the first store
+  constexpr int U = 4;
+  const size_t stride = (size_t)gridDim.x * BT;
+  for (size_t i0 = (size_t)blockIdx.x * BT + threadIdx.x; i0 < a.n; i0 += U * stride) {
+    C64 pp[U], qq[U], vv[U], ww[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = i0 + u * stride;
+      if (i < a.n) {
+        pp[u] = p[i];
+        qq[u] = q[i];
+        vv[u] = v[i];
+        ww[u] = w[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = i0 + u * stride;
+      if (i < a.n) {
+        const C64 vr = pp[u] - cmul(av, vv[u]);
+        const C64 wr = qq[u] - cmul(aw, ww[u]);
+        vn[i] = vr;
+        wn[i] = wr;
+        const C64 t = cmulc(wr, vr);
+        sre += t.re;
+        sim += t.im;
+        nv += norm2(vr);
+        nw += norm2(wr);
+        if (lift) y[i] = y[i] + cmul(lcn, vr);
+      }
+    }
   }
   double t4[4] = {sre, sim, nv, nw};
   bsum<4>(t4);
@@ -350,14 +339,17 @@ int nb_elem_b(size_t n) {
 }
 
 // one sweep of the basis for every source: steps 0 .. kmax - 1
-int sweep(nk_lattice* lat, const BArgs& a, double m_w, double mu, int kmax, hipStream_t st) {
+int sweep(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int kmax, hipStream_t st) {
   const Geom& g = lat->g;
   const LinksPlain<double> lk{lat->U64.as<C64>(), g.V};
   hipLaunchKernelGGL(k_bstart, dim3(a.nb2, a.r), dim3(BT), 0, st, a);
   hipLaunchKernelGGL(k_bred2, dim3(a.r), dim3(BT), 0, st, a, 0);
   const double eft = exp(mu), ebt = exp(-mu);
   for (int j = 0; j < kmax; ++j) {
-    hipLaunchKernelGGL(k_blk1, dim3(a.nb1), dim3(BT), 0, st, g, lk, 4.0 + m_w, eft, ebt, j, a);
+    if (ng == 2)
+      hipLaunchKernelGGL(k_blk1<2>, dim3(a.nb1, a.r), dim3(BT), 0, st, g, lk, 4.0 + m_w, eft, ebt, j, a);
+    else
+      hipLaunchKernelGGL(k_blk1<4>, dim3(a.nb1, a.r), dim3(BT), 0, st, g, lk, 4.0 + m_w, eft, ebt, j, a);
     hipLaunchKernelGGL(k_bred1, dim3(a.r), dim3(BT), 0, st, a, j);
     hipLaunchKernelGGL(k_blk2, dim3(a.nb2, a.r), dim3(BT), 0, st, a, j);
     if (j + 1 < kmax) hipLaunchKernelGGL(k_bred2, dim3(a.r), dim3(BT), 0, st, a, j + 1);
@@ -366,28 +358,58 @@ int sweep(nk_lattice* lat, const BArgs& a, double m_w, double mu, int kmax, hipS
   return NK_OK;
 }
 
+// the same sweep replayed from a HIP graph captured on first use (on a
+// private stream) and cached on the handle under its launch arguments; the
+// sweep has kernel launches only, so every replay is the same work as the
+// direct launches, bit for bit
+int sweep_graph(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int kmax, hipStream_t st) {
+  // the key: every launch argument, field by field (no padding bytes)
+  std::vector<char> kb;
+  auto put = [&](const auto& v) {
+    const char* c = reinterpret_cast<const char*>(&v);
+    kb.insert(kb.end(), c, c + sizeof v);
+  };
+  put(a.base), put(a.n), put(a.nslots), put(a.ncols), put(a.store), put(a.r), put(a.k);
+  put(a.alpha), put(a.beta), put(a.delta), put(a.sv), put(a.sw), put(a.flags), put(a.part1), put(a.part2);
+  put(a.nb1), put(a.nb2), put(a.lc), put(a.kused), put(ng), put(kmax), put(m_w), put(mu);
+  put(lat->U64.p), put(lat->g.V);
+  hipGraphExec_t exec = nullptr;
+  for (auto& gr : lat->graphs)
+    if (gr.key == kb) exec = gr.exec;
+  if (!exec) {
+    if (!lat->cap_stream) NK_HIP(hipStreamCreateWithFlags(&lat->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    NK_HIP(hipStreamBeginCapture(lat->cap_stream, hipStreamCaptureModeRelaxed));
+    const int e = sweep(lat, a, ng, m_w, mu, kmax, lat->cap_stream);
+    const hipError_t ec = hipStreamEndCapture(lat->cap_stream, &graph);
+    if (e) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e;
+    }
+    NK_HIP(ec);
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    NK_HIP(ei);
+    if (lat->graphs.size() >= 4) {  // keep the four most recent
+      (void)hipGraphExecDestroy(lat->graphs.front().exec);
+      lat->graphs.erase(lat->graphs.begin());
+    }
+    lat->graphs.push_back({kb, exec});
+  }
+  NK_HIP(hipGraphLaunch(exec, st));
+  return NK_OK;
+}
+
 }  // namespace
 
-int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64* y_canon, nk_sign_info* info,
-               hipStream_t st) {
+// sources [0, r) of x_canon / y_canon with inner sizes ell[], V_k stored
+// (store = 1) or rebuilt in a second sweep
+static int block_range(nk_lattice* lat, const nk_sign_params* p, const int* ell, int r, int store,
+                       const C64* x_canon, C64* y_canon, nk_sign_info* info, hipStream_t st) {
   const Geom& g = lat->g;
-  const int r = p->nrhs, k = p->k;
-  if (p->mu == 0.0 || p->precision != NK_PREC_FP64 || p->tol > 0.0) return 1;  // not covered: one at a time
+  const int k = p->k;
   const size_t n = (size_t)12 * g.V;
   const size_t colbytes = n * sizeof(C64);
-  std::vector<int> ell(r);
-  for (int s = 0; s < r; ++s) ell[s] = std::min(p->ell_per_rhs ? p->ell_per_rhs[s] : p->ell, k);
-  // store every column when it fits, else rebuild the basis in a second sweep
-  size_t fr = 0, tot = 0;
-  NK_HIP(hipMemGetInfo(&fr, &tot));
-  const size_t avail = fr + lat->bvec.bytes;
-  const size_t margin = (size_t)4 << 30;
-  const size_t store_bytes = (size_t)r * (k + 7) * colbytes;
-  int store = p->two_pass == NK_TWO_PASS_ON ? 0 : (store_bytes + margin <= avail ? 1 : 0);
-  if (!store && p->two_pass == NK_TWO_PASS_OFF) {
-    set_error("the bases of %d sources need %zu bytes; %zu available and two_pass is OFF", r, store_bytes, avail);
-    return NK_ENOMEM;
-  }
   BArgs a{};
   a.n = n;
   a.ncols = store ? k + 1 : 3;
@@ -395,7 +417,11 @@ int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64
   a.store = store;
   a.r = r;
   a.k = k;
-  a.nb1 = (g.V + 31) / 32;
+  // direction groups of the stencil kernel: the autotuner's choice for the
+  // one-source FP64 two-sided kernel when it has run on this handle
+  const int tuned = lat->k1_groups[0][NK_PREC_FP64];
+  const int ng = tuned ? tuned : NK_GROUPS;
+  a.nb1 = (g.V + 32 * (4 / ng) - 1) / (32 * (4 / ng));
   a.nb2 = nb_elem_b(n);
   if (lat->bvec.ensure((size_t)r * a.nslots * colbytes)) return NK_ENOMEM;
   a.base = lat->bvec.as<C64>();
@@ -461,7 +487,11 @@ int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64
   NK_HIP(hipMemsetAsync(a.flags, 0, r * sizeof(int), st));
   NK_HIP(hipMemsetAsync(a.beta, 0, (size_t)r * k * sizeof(C64), st));
   NK_HIP(hipMemsetAsync(a.delta, 0, (size_t)r * k * sizeof(C64), st));
-  if (int e = sweep(lat, a, p->m_w, p->mu, k, st)) return e;
+  auto run_sweep = [&](const BArgs& args, int kmax) {
+    return p->block == 2 ? sweep_graph(lat, args, ng, p->m_w, p->mu, kmax, st)
+                         : sweep(lat, args, ng, p->m_w, p->mu, kmax, st);
+  };
+  if (int e = run_sweep(a, k)) return e;
   NK_HIP(hipEventRecord(ev[1], st));
 
   // steps each source completed
@@ -539,7 +569,7 @@ int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64
     NK_HIP(hipMemsetAsync(a.flags, 0, r * sizeof(int), st));
     int kmax = 0;
     for (int s = 0; s < r; ++s) kmax = std::max(kmax, kus[s]);
-    if (int e = sweep(lat, b, p->m_w, p->mu, kmax - 1 > 0 ? kmax - 1 : 0, st)) return e;
+    if (int e = run_sweep(b, kmax - 1 > 0 ? kmax - 1 : 0)) return e;
   }
   for (int s = 0; s < r; ++s) {
     const C64* y = a.base + ((size_t)s * a.nslots + a.ncols + 5) * n;
@@ -564,6 +594,47 @@ int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64
     info->t_lift_ms = t2;
   }
   return warn;
+}
+
+int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64* y_canon, nk_sign_info* info,
+               hipStream_t st) {
+  const int r = p->nrhs, k = p->k;
+  if (p->mu == 0.0 || p->precision != NK_PREC_FP64 || p->tol > 0.0) return 1;  // not covered: one at a time
+  const size_t n = (size_t)12 * lat->g.V;
+  std::vector<int> ell(r);
+  for (int s = 0; s < r; ++s) ell[s] = std::min(p->ell_per_rhs ? p->ell_per_rhs[s] : p->ell, k);
+  if (p->two_pass == NK_TWO_PASS_ON) return block_range(lat, p, ell.data(), r, 0, x_canon, y_canon, info, st);
+  // store every basis when they fit; else as many sources at a time as fit
+  // with stored bases (a stored basis costs one sweep, a rebuilt one two);
+  // only when not even two fit, rebuild them all in a second sweep
+  const size_t per_src = (size_t)(k + 7) * n * sizeof(C64);
+  const size_t margin = (size_t)4 << 30;
+  size_t fr = 0, tot = 0;
+  NK_HIP(hipMemGetInfo(&fr, &tot));
+  size_t avail = fr + lat->bvec.bytes;
+  if ((size_t)r * per_src + margin > avail && lat->vk.bytes) {  // the one-source basis is not needed here
+    lat->vk.release();
+    NK_HIP(hipMemGetInfo(&fr, &tot));
+    avail = fr + lat->bvec.bytes;
+  }
+  const long fit = avail > margin ? (long)((avail - margin) / per_src) : 0;
+  if (fit >= r) return block_range(lat, p, ell.data(), r, 1, x_canon, y_canon, info, st);
+  if (fit < 2) {
+    if (p->two_pass == NK_TWO_PASS_OFF) {
+      set_error("a stored basis needs %zu bytes per source; %zu available and two_pass is OFF", per_src, avail);
+      return NK_ENOMEM;
+    }
+    return block_range(lat, p, ell.data(), r, 0, x_canon, y_canon, info, st);
+  }
+  int worst = NK_OK;
+  for (int c0 = 0; c0 < r; c0 += (int)fit) {
+    const int cnt = std::min((int)fit, r - c0);
+    const int e = block_range(lat, p, ell.data() + c0, cnt, 1, x_canon + (size_t)c0 * n, y_canon + (size_t)c0 * n,
+                              info, st);
+    if (e < 0) return e;
+    worst = std::max(worst, e);
+  }
+  return worst;
 }
 
 }  // namespace nk

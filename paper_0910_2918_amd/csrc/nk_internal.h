@@ -135,6 +135,13 @@ struct nk_lattice {
   nk::DevBuf tmp;      // device-layout temporaries of the stand-alone operator calls
   nk::DevBuf bvec;     // multi-source path: per-source vectors (basis, W ring, p, q, x, y)
   nk::DevBuf bsmall;   // multi-source path: coefficients, partial sums, small problems
+  // multi-source path: sweeps captured as HIP graphs, keyed by their launch arguments
+  struct Graph {
+    std::vector<char> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t cap_stream = nullptr;  // private stream the sweeps are captured on
   // autotuned direction groups of the outer-recurrence stencil kernel,
   // [hermitian][precision]; 0 = not tuned yet
   int k1_groups[2][3] = {{0, 0, 0}, {0, 0, 0}};

@@ -266,56 +266,6 @@ __device__ __forceinline__ void hop_bwd(const Geom& g, int s, const SiteC& sc0, 
   pin<R, NF>(acc);
 }
 
-// --- hops with the links already in registers ------------------------------
-// The multi-source kernels load a site's links of one direction once and
-// apply them to every source.
-
-// neighbours, boundary signs and both links of direction NU at site s
-template <int NU, class R, class LK>
-__device__ __forceinline__ void hop_setup(const Geom& g, int s, const SiteC& x, const LK& lk, Cx<R> (&uf)[9],
-                                          Cx<R> (&ub)[9], int& sf, int& sb, R& wf, R& wb) {
-  bool wrap;
-  sf = nbr_fwd<NU>(g, s, x, &wrap);
-  wf = (NU == 3 && wrap) ? R(-1) : R(1);
-  sb = nbr_bwd<NU>(g, s, x, &wrap);
-  wb = (NU == 3 && wrap) ? R(-1) : R(1);
-  lk.load(NU, s, uf);
-  lk.load(NU, sb, ub);
-}
-
-// FWD: sc (1 - gamma_NU) u psi(sn); otherwise sc (1 + gamma_NU) u^dag psi(sn)
-template <int NU, bool FWD, class R>
-__device__ __forceinline__ void hop_with(const Cx<R> (&u)[9], const Cx<R>* __restrict__ in, int V, int sn, R sc,
-                                         Cx<R> (&acc)[12]) {
-  using P = Proj<NU>;
-  Cx<R> p[12];
-  load_spinor(in, V, sn, p);
-  Cx<R> h0[3], h1[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const Cx<R> t0 = mulu<P::c0r, P::c0i>(p[P::p0 * 3 + c]);
-    const Cx<R> t1 = mulu<P::c1r, P::c1i>(p[P::p1 * 3 + c]);
-    h0[c] = sc * (FWD ? p[c] + t0 : p[c] - t0);
-    h1[c] = sc * (FWD ? p[3 + c] + t1 : p[3 + c] - t1);
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    Cx<R> g0, g1;
-    if (FWD) {
-      g0 = cmul(u[a * 3 + 0], h0[0]) + cmul(u[a * 3 + 1], h0[1]) + cmul(u[a * 3 + 2], h0[2]);
-      g1 = cmul(u[a * 3 + 0], h1[0]) + cmul(u[a * 3 + 1], h1[1]) + cmul(u[a * 3 + 2], h1[2]);
-    } else {
-      g0 = cmulc(u[0 * 3 + a], h0[0]) + cmulc(u[1 * 3 + a], h0[1]) + cmulc(u[2 * 3 + a], h0[2]);
-      g1 = cmulc(u[0 * 3 + a], h1[0]) + cmulc(u[1 * 3 + a], h1[1]) + cmulc(u[2 * 3 + a], h1[2]);
-    }
-    const Cx<R> l0 = mulu<P::c0r, -P::c0i>(g0), l1 = mulu<P::c1r, -P::c1i>(g1);
-    acc[a] = acc[a] + g0;
-    acc[3 + a] = acc[3 + a] + g1;
-    acc[P::p0 * 3 + a] = FWD ? acc[P::p0 * 3 + a] + l0 : acc[P::p0 * 3 + a] - l0;
-    acc[P::p1 * 3 + a] = FWD ? acc[P::p1 * 3 + a] + l1 : acc[P::p1 * 3 + a] - l1;
-  }
-}
-
 // --- direction groups over the waves of a workgroup -------------------------
 // The stencil kernels give each site's eight hops to NG waves of a 256-thread
 // workgroup: wave w takes direction group w % NG (NG = 4: one direction,

@@ -115,3 +115,27 @@ def test_block_8x4_sixteen_sources_uneven_ell():
         eps_true = rel(ys[s], yt[s])
         assert rel(yb[s], ys[s]) <= max(1e-10, 10 * eps_true), (s, rel(yb[s], ys[s]), eps_true)
     lat.close()
+
+
+def test_block_graph_replays_match_direct_launches(setup):
+    """block = 2 replays each sweep from a captured HIP graph: every replay,
+    with eager work and synchronisations between them, gives the same bits
+    as the direct launches (block = 1)."""
+    lat, u, xs = setup
+    b = nk()
+    torch = torch_cuda()
+    ells = [20, 45, 80, 33]
+    banner("block graph replays vs direct launches")
+    yd, _, _ = _run(lat, xs, k=120, ell_per_rhs=ells, block=1)
+    for rep in range(3):
+        yg, _, rc = _run(lat, xs, k=120, ell_per_rhs=ells, block=2)
+        assert rc == 0
+        assert np.array_equal(yg, yd), rep
+        # eager work between the replays
+        yo, _, _ = _run(lat, xs[:1], k=60, ell=20)
+        torch.cuda.synchronize()
+    # the two-pass sweeps (two different graphs) as well
+    yd2, _, _ = _run(lat, xs, k=120, ell_per_rhs=ells, block=1, two_pass=1)
+    for rep in range(2):
+        yg2, _, _ = _run(lat, xs, k=120, ell_per_rhs=ells, block=2, two_pass=1)
+        assert np.array_equal(yg2, yd2), rep
