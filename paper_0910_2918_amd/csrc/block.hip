@@ -513,22 +513,18 @@ static int block_range(nk_lattice* lat, const nk_sign_params* p, const int* ell,
   // small problems: one inner projection per source, one batched Roberts-Higham
   std::vector<C64> hab((size_t)r * 3 * ld, mk(0.0, 0.0));
   if (nested) {
-    std::vector<C64> hl((size_t)3 * ld);
+    std::vector<const C64*> pa(r), pb(r), pd(r);
+    std::vector<int> ls(r);
     for (int s = 0; s < r; ++s) {
-      SmallOut so;
-      so.hl_host = hl.data();
-      so.vl_dev = Vl + (size_t)s * k * ld;
-      so.inner_only = true;
-      const int e = small_sign_dev(kus[s], std::min(ell[s], kus[s]), 0, a.alpha + (size_t)s * k,
-                                   a.beta + (size_t)s * k, a.delta + (size_t)s * k, p->rh_scaling, p->rh_maxit,
-                                   p->rh_tol, z, &so, st);
-      if (e < 0) return e;
-      if (e > 0 && warn == NK_OK) warn = e;
-      lus[s] = so.ell_used;
-      for (int t = 0; t < 3; ++t)
-        std::copy(hl.begin() + (size_t)t * lus[s], hl.begin() + (size_t)(t + 1) * lus[s],
-                  hab.begin() + (size_t)s * 3 * ld + (size_t)t * ld);
+      pa[s] = a.alpha + (size_t)s * k;
+      pb[s] = a.beta + (size_t)s * k;
+      pd[s] = a.delta + (size_t)s * k;
+      ls[s] = std::min(ell[s], kus[s]);
     }
+    const int e = small_inner_batch(r, kus.data(), ls.data(), 0, pa.data(), pb.data(), pd.data(), hab.data(), ld, Vl,
+                                    (size_t)k * ld, lus.data(), st);
+    if (e < 0) return e;
+    if (e > 0 && warn == NK_OK) warn = e;
     NK_HIP(hipMemcpyAsync(abd, hab.data(), hab.size() * sizeof(C64), hipMemcpyHostToDevice, st));
   } else {
     for (int s = 0; s < r; ++s) {

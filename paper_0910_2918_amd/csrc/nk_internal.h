@@ -217,6 +217,11 @@ struct SmallOut {
 int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,
                    int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st);
 
+// the inner projections of r problems at once (see small.hip)
+int small_inner_batch(int r, const int* k, const int* ell, int hermitian, const C64* const* alpha,
+                      const C64* const* beta, const C64* const* delta, C64* hl_host, int ldh, C64* vl_dev,
+                      size_t vl_stride, int* ell_used, hipStream_t st);
+
 // rh.hip -- batched Roberts-Higham on dense matrices (S on the device, row-major,
 // matrix b at b * ld * ld)
 int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,

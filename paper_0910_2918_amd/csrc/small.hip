@@ -12,6 +12,7 @@
 // H x = e_j for every column j at once and write B densely; the inner
 // iteration then only needs dense mat-vecs with B (and B^dag), which spread
 // over the whole GPU, instead of k-long sequential solves inside its loop.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -218,8 +219,12 @@ __device__ __forceinline__ void bsum(double (&v)[4]) {
   }
 }
 
-__global__ void __launch_bounds__(GR * 64) k_in_gemv(Inner s, int i) {
-  if (s.flags[0]) return;
+// Every inner kernel serves a batch of independent problems: problem
+// blockIdx.z is SS[blockIdx.z]; the grid is sized for the largest, and a
+// workgroup beyond its own problem's size or steps returns at once.
+__global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ SS, int i) {
+  const Inner& s = SS[blockIdx.z];
+  if (i >= s.lmax || (int)blockIdx.x >= s.nb1 || s.flags[0]) return;
   const int k = s.k;
   const int side = blockIdx.y;  // 0: u = B v, 1: q = B^dag w
   const C64* src = side ? s.qraw[i & 1] : s.uraw[i & 1];
@@ -301,8 +306,9 @@ __global__ void __launch_bounds__(GR * 64) k_in_gemv(Inner s, int i) {
 
 // pass 1 (last == 0): reduce part1, subtract, emit part2;
 // pass 2 (last == 1): reduce part2, subtract, emit the normalisation sums
-__global__ void __launch_bounds__(ST) k_in_sub(Inner s, int i, int last) {
-  if (s.flags[0]) return;
+__global__ void __launch_bounds__(ST) k_in_sub(const Inner* __restrict__ SS, int i, int last) {
+  const Inner& s = SS[blockIdx.z];
+  if (i >= s.lmax || (last && i + 1 >= s.lmax) || (int)blockIdx.x >= s.nb2 || s.flags[0]) return;
   const int k = s.k;
   const int sides = s.herm ? 1 : 2;
   __shared__ C64 s_c[2][LMAX];
@@ -415,7 +421,84 @@ __global__ void k_col0(int k, const C64* __restrict__ S, C64* __restrict__ z) {
 
 // ---------------------------------------------------------------------------
 namespace {
-DevBuf g_small;
+DevBuf g_small, g_batch;
+}
+
+// device pointers of the tridiagonal factorisation of H_k
+struct TriWork {
+  C64 *Lm, *U0i, *U1, *U2;
+  int* Sw;
+};
+
+// workspace of one inner problem of order k with ell steps, carved from base
+// (base == nullptr: only the size); fills s and tw
+static size_t inner_layout(int k, int ell, int hermitian, char* base, Inner* s, TriWork* tw) {
+  const int nb1 = (k + GR - 1) / GR, nb2 = (k + SR - 1) / SR;
+  const size_t kk = (size_t)k * k;
+  size_t bytes = 0;
+  auto take = [&](size_t b) {
+    size_t o = bytes;
+    bytes += (b + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t oB = take(kk * sizeof(C64));
+  const size_t oBH = take(hermitian ? 0 : kk * sizeof(C64));
+  const size_t oV = take((size_t)k * ell * sizeof(C64));
+  const size_t oW = take(hermitian ? 0 : (size_t)k * ell * sizeof(C64));
+  const size_t oR = take((size_t)4 * k * sizeof(C64));
+  const size_t oF = take((size_t)5 * k * sizeof(C64) + (size_t)k * sizeof(int));
+  const size_t oC = take((size_t)3 * ell * sizeof(C64));
+  const size_t oP1 = take((size_t)2 * nb1 * ell * sizeof(C64));
+  const size_t oP2 = take((size_t)2 * nb2 * ell * sizeof(C64));
+  const size_t oP3 = take((size_t)4 * nb2 * sizeof(double));
+  const size_t oI = take(8 * sizeof(int));
+  if (!base) return bytes;
+  s->k = k;
+  s->herm = hermitian;
+  s->lmax = ell;
+  s->B = (C64*)(base + oB);
+  s->BH = hermitian ? s->B : (C64*)(base + oBH);
+  s->V = (C64*)(base + oV);
+  s->W = hermitian ? s->V : (C64*)(base + oW);
+  C64* R = (C64*)(base + oR);
+  s->uraw[0] = R;
+  s->uraw[1] = R + k;
+  s->qraw[0] = R + 2 * k;
+  s->qraw[1] = R + 3 * k;
+  C64* F = (C64*)(base + oF);
+  tw->Lm = F;
+  tw->U0i = F + k;
+  tw->U1 = F + 2 * k;
+  tw->U2 = F + 3 * k;
+  tw->Sw = (int*)(F + 5 * k);
+  C64* Cc = (C64*)(base + oC);
+  s->a = Cc;
+  s->b = Cc + ell;
+  s->d = Cc + 2 * ell;
+  s->part1 = (C64*)(base + oP1);
+  s->part2 = (C64*)(base + oP2);
+  s->part3 = (double*)(base + oP3);
+  s->nb1 = nb1;
+  s->nb2 = nb2;
+  s->flags = (int*)(base + oI);
+  return bytes;
+}
+
+// B = H_k + H_k^{-1} (and B^dag) of one problem; clears its flags and b
+static int inner_prepare(int k, int hermitian, const C64* alpha, const C64* beta, const C64* delta, const Inner& s,
+                         const TriWork& tw, hipStream_t st) {
+  NK_HIP(hipMemsetAsync(s.flags, 0, 8 * sizeof(int), st));
+  NK_HIP(hipMemsetAsync(s.b, 0, 2 * s.lmax * sizeof(C64), st));
+  const size_t lds_lu = k <= TRI_LDS_MAX ? (size_t)3 * k * sizeof(C64) : 0;
+  const size_t lds_inv = k <= TRI_INV_LDS_MAX ? (size_t)k * sizeof(TriF) : 0;
+  hipLaunchKernelGGL(k_tri_lu, dim3(1), dim3(256), lds_lu, st, k, alpha, beta, delta, tw.Lm, tw.Sw, tw.U0i, tw.U1,
+                     tw.U2, s.flags + 1);
+  hipLaunchKernelGGL(k_tri_inv, dim3((k + 63) / 64), dim3(64), lds_inv, st, k, tw.Lm, tw.Sw, tw.U0i, tw.U1, tw.U2,
+                     alpha, beta, delta, (C64*)s.B);
+  if (!hermitian)
+    hipLaunchKernelGGL(k_adjoint, dim3((k + 31) / 32, (k + 31) / 32), dim3(32, 8), 0, st, k, s.B, (C64*)s.BH);
+  NK_HIP(hipGetLastError());
+  return NK_OK;
 }
 
 int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,
@@ -446,75 +529,26 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     set_error("inner Krylov size %d exceeds %d", ell, LMAX);
     return NK_EINVAL;
   }
-  const int nb1 = (k + GR - 1) / GR, nb2 = (k + SR - 1) / SR;
-  const size_t kk = (size_t)k * k;
-  size_t bytes = 0;
-  auto take = [&](size_t b) {
-    size_t o = bytes;
-    bytes += (b + 255) & ~(size_t)255;
-    return o;
-  };
-  const size_t oB = take(kk * sizeof(C64));
-  const size_t oBH = take(hermitian ? 0 : kk * sizeof(C64));
-  const size_t oV = take((size_t)k * ell * sizeof(C64));
-  const size_t oW = take(hermitian ? 0 : (size_t)k * ell * sizeof(C64));
-  const size_t oR = take((size_t)4 * k * sizeof(C64));
-  const size_t oF = take((size_t)5 * k * sizeof(C64) + (size_t)k * sizeof(int));
-  const size_t oC = take((size_t)3 * ell * sizeof(C64));
-  const size_t oP1 = take((size_t)2 * nb1 * ell * sizeof(C64));
-  const size_t oP2 = take((size_t)2 * nb2 * ell * sizeof(C64));
-  const size_t oP3 = take((size_t)4 * nb2 * sizeof(double));
-  const size_t oS = take((size_t)ell * ell * sizeof(C64));
-  const size_t oI = take(8 * sizeof(int));
-  if (g_small.ensure(bytes)) return NK_ENOMEM;
+  const size_t lay = inner_layout(k, ell, hermitian, nullptr, nullptr, nullptr);
+  const size_t oS = (lay + 255) & ~(size_t)255;
+  const size_t oD = oS + (((size_t)ell * ell * sizeof(C64) + 255) & ~(size_t)255);
+  if (g_small.ensure(oD + 256)) return NK_ENOMEM;
   char* base = g_small.as<char>();
   Inner s;
-  s.k = k;
-  s.herm = hermitian;
-  s.lmax = ell;
-  s.B = (C64*)(base + oB);
-  s.BH = hermitian ? s.B : (C64*)(base + oBH);
-  s.V = (C64*)(base + oV);
-  s.W = hermitian ? s.V : (C64*)(base + oW);
-  C64* R = (C64*)(base + oR);
-  s.uraw[0] = R;
-  s.uraw[1] = R + k;
-  s.qraw[0] = R + 2 * k;
-  s.qraw[1] = R + 3 * k;
-  C64* F = (C64*)(base + oF);
-  C64 *Lm = F, *U0i = F + k, *U1 = F + 2 * k, *U2 = F + 3 * k;
-  int* Sw = (int*)(F + 5 * k);
-  C64* Cc = (C64*)(base + oC);
-  s.a = Cc;
-  s.b = Cc + ell;
-  s.d = Cc + 2 * ell;
-  s.part1 = (C64*)(base + oP1);
-  s.part2 = (C64*)(base + oP2);
-  s.part3 = (double*)(base + oP3);
-  s.nb1 = nb1;
-  s.nb2 = nb2;
+  TriWork tw;
+  inner_layout(k, ell, hermitian, base, &s, &tw);
   C64* Hl = (C64*)(base + oS);
-  int* iflags = (int*)(base + oI);
-  s.flags = iflags;
-  NK_HIP(hipMemsetAsync(iflags, 0, 8 * sizeof(int), st));
-  NK_HIP(hipMemsetAsync(s.b, 0, 2 * ell * sizeof(C64), st));
-
-  const size_t lds_lu = k <= TRI_LDS_MAX ? (size_t)3 * k * sizeof(C64) : 0;
-  const size_t lds_inv = k <= TRI_INV_LDS_MAX ? (size_t)k * sizeof(TriF) : 0;
-  hipLaunchKernelGGL(k_tri_lu, dim3(1), dim3(256), lds_lu, st, k, alpha, beta, delta, Lm, Sw, U0i, U1, U2,
-                     iflags + 1);
-  hipLaunchKernelGGL(k_tri_inv, dim3((k + 63) / 64), dim3(64), lds_inv, st, k, Lm, Sw, U0i, U1, U2, alpha, beta,
-                     delta, (C64*)s.B);
-  if (!hermitian) hipLaunchKernelGGL(k_adjoint, dim3((k + 31) / 32, (k + 31) / 32), dim3(32, 8), 0, st, k, s.B,
-                                     (C64*)s.BH);
-  NK_HIP(hipGetLastError());
+  Inner* sdev = (Inner*)(base + oD);
+  NK_HIP(hipMemcpyAsync(sdev, &s, sizeof s, hipMemcpyHostToDevice, st));
+  if (int e = inner_prepare(k, hermitian, alpha, beta, delta, s, tw, st)) return e;
   const int sides = hermitian ? 1 : 2;
   for (int i = 0; i < ell; ++i) {
-    hipLaunchKernelGGL(k_in_gemv, dim3(nb1, sides), dim3(GR * 64), 0, st, s, i);
-    hipLaunchKernelGGL(k_in_sub, dim3(nb2), dim3(ST), 0, st, s, i, 0);
-    if (i + 1 < ell) hipLaunchKernelGGL(k_in_sub, dim3(nb2), dim3(ST), 0, st, s, i, 1);
+    hipLaunchKernelGGL(k_in_gemv, dim3(s.nb1, sides, 1), dim3(GR * 64), 0, st, sdev, i);
+    hipLaunchKernelGGL(k_in_sub, dim3(s.nb2, 1, 1), dim3(ST), 0, st, sdev, i, 0);
+    if (i + 1 < ell) hipLaunchKernelGGL(k_in_sub, dim3(s.nb2, 1, 1), dim3(ST), 0, st, sdev, i, 1);
   }
   NK_HIP(hipGetLastError());
+  int* iflags = s.flags;
   int fl[2] = {0, 0};
   NK_HIP(hipMemcpyAsync(fl, iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   NK_HIP(hipStreamSynchronize(st));
@@ -549,6 +583,67 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     out->rh_residual = res;
   }
   return e ? e : (fl[0] ? NK_WARN_BREAKDOWN : NK_OK);
+}
+
+// The inner projections of r problems at once: one launch per kernel and
+// step serves all of them (grid z = problem).  Problem s has order k[s] and
+// ell[s] steps; its H_ell (diagonal, super-, sub-diagonal) goes to
+// hl_host + s * 3 * ldh (rows of ldh) and its basis V_ell (column j at
+// j * k[s]) to vl_dev + s * vl_stride; ell_used[s] < ell[s] after an
+// invariant subspace or a breakdown.
+int small_inner_batch(int r, const int* k, const int* ell, int hermitian, const C64* const* alpha,
+                      const C64* const* beta, const C64* const* delta, C64* hl_host, int ldh, C64* vl_dev,
+                      size_t vl_stride, int* ell_used, hipStream_t st) {
+  std::vector<size_t> off(r + 1, 0);
+  for (int s = 0; s < r; ++s) {
+    if (ell[s] < 1 || ell[s] > LMAX || ell[s] > k[s] || ell[s] > ldh) {
+      set_error("inner problem %d: ell = %d outside [1, min(k = %d, %d)]", s, ell[s], k[s], LMAX);
+      return NK_EINVAL;
+    }
+    off[s + 1] = off[s] + ((inner_layout(k[s], ell[s], hermitian, nullptr, nullptr, nullptr) + 255) & ~(size_t)255);
+  }
+  if (g_batch.ensure(off[r] + (size_t)r * sizeof(Inner) + 256)) return NK_ENOMEM;
+  char* base = g_batch.as<char>();
+  std::vector<Inner> S(r);
+  std::vector<TriWork> tw(r);
+  int lmax = 0, nb1 = 0, nb2 = 0;
+  for (int s = 0; s < r; ++s) {
+    inner_layout(k[s], ell[s], hermitian, base + off[s], &S[s], &tw[s]);
+    if (int e = inner_prepare(k[s], hermitian, alpha[s], beta[s], delta[s], S[s], tw[s], st)) return e;
+    lmax = std::max(lmax, ell[s]);
+    nb1 = std::max(nb1, S[s].nb1);
+    nb2 = std::max(nb2, S[s].nb2);
+  }
+  Inner* sdev = (Inner*)(base + off[r]);
+  NK_HIP(hipMemcpyAsync(sdev, S.data(), r * sizeof(Inner), hipMemcpyHostToDevice, st));
+  const int sides = hermitian ? 1 : 2;
+  for (int i = 0; i < lmax; ++i) {
+    hipLaunchKernelGGL(k_in_gemv, dim3(nb1, sides, r), dim3(GR * 64), 0, st, sdev, i);
+    hipLaunchKernelGGL(k_in_sub, dim3(nb2, 1, r), dim3(ST), 0, st, sdev, i, 0);
+    if (i + 1 < lmax) hipLaunchKernelGGL(k_in_sub, dim3(nb2, 1, r), dim3(ST), 0, st, sdev, i, 1);
+  }
+  NK_HIP(hipGetLastError());
+  std::vector<int> fl((size_t)2 * r);
+  for (int s = 0; s < r; ++s) NK_HIP(hipMemcpyAsync(&fl[2 * s], S[s].flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));
+  int warn = NK_OK;
+  for (int s = 0; s < r; ++s) {
+    if (fl[2 * s + 1]) {
+      set_error("nested small problem %d: H_k is singular", s);
+      return NK_WARN_NOTCONV;
+    }
+    const int lu = fl[2 * s] ? fl[2 * s] : ell[s];
+    if (fl[2 * s]) warn = NK_WARN_BREAKDOWN;
+    ell_used[s] = lu;
+    C64* h = hl_host + (size_t)s * 3 * ldh;
+    NK_HIP(hipMemcpyAsync(h, S[s].a, lu * sizeof(C64), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(h + ldh, S[s].b, lu * sizeof(C64), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(h + 2 * ldh, S[s].d, lu * sizeof(C64), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(vl_dev + (size_t)s * vl_stride, S[s].V, (size_t)k[s] * lu * sizeof(C64),
+                          hipMemcpyDeviceToDevice, st));
+  }
+  NK_HIP(hipStreamSynchronize(st));
+  return warn;
 }
 
 }  // namespace nk
