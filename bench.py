@@ -41,7 +41,7 @@ K1_BYTES_PER_SITE = 576 + 4 * 192 + 2 * 192
 # every launch would slow the timed run itself by about 15%)
 PROFILE_EVERY = 10
 HBM_PEAK_GBS = 8000.0
-PROFILE_PMC = os.path.join(ROOT, "profiles", "k_bil1w_16x16x16x16_pmc.json")
+PROFILE_PMC = os.path.join(ROOT, "profiles", "k_bil1_16x16x16x16_pmc.json")
 
 
 def kernel_source_hash() -> str:
@@ -119,6 +119,7 @@ def main() -> int:
     ap.add_argument("--ell", type=int, default=84)
     ap.add_argument("--kref-extra", type=int, default=500)
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=8, help="sources of the lockstep run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--target", type=float, default=1e-8)
     ap.add_argument("--probe", action="store_true",
@@ -134,6 +135,7 @@ def main() -> int:
                           "n_gpus": args.gpus}))
         return 2
 
+    import numpy as np
     import torch
 
     import latgen
@@ -151,8 +153,17 @@ def main() -> int:
     y = torch.empty_like(x)
     yref = torch.empty_like(x)
 
-    def params(k, ell, profile=0):
-        return nk.nk_sign_params_default(k=k, ell=ell, mu=MU, m_w=M_W, profile=profile)
+    def params(k, ell, profile=0, scaling=0, nrhs=1, block=0):
+        return nk.nk_sign_params_default(k=k, ell=ell, mu=MU, m_w=M_W, profile=profile, rh_scaling=scaling,
+                                         nrhs=nrhs, block=block)
+
+    # the learned Roberts-Higham scaling (trained weights shipped with the package)
+    from paper_0910_2918_amd import rh_train
+
+    have_model = os.path.exists(rh_train.WEIGHTS)
+    if have_model:
+        nk.nk_rh_model_set(np.load(rh_train.WEIGHTS).astype(np.float32))
+    LEARNED = nk.NK_RH_LEARNED if have_model else nk.NK_RH_NONE
 
     if args.probe:
         n = 1024 * 1024 * 1024 // 16
@@ -190,44 +201,66 @@ def main() -> int:
     # accuracy, untimed: reference = non-nested at k + kref_extra
     kref = args.k + args.kref_extra
     nk.nk_sign_apply_device(lat.h, params(kref, 0), x, yref)
-    nk.nk_sign_apply_device(lat.h, params(args.k, args.ell), x, y)
+    nk.nk_sign_apply_device(lat.h, params(args.k, args.ell, scaling=LEARNED), x, y)
     eps_nested = rel(y, yref)
     nk.nk_sign_apply_device(lat.h, params(args.k, 0), x, y)
     eps_plain = rel(y, yref)
 
-    # nested: warmup, then K timed steps (kernel durations recorded with HIP events)
+    def timed(nsteps, **kw):
+        """Wall time per application over nsteps after one warm-up; summed info fields."""
+        nk.nk_sign_apply_device(lat.h, params(**kw), x, y)
+        torch.cuda.synchronize()
+        acc = {"t_stencil_ms": 0.0, "n_stencil": 0, "t_update_ms": 0.0, "n_update": 0, "t_basis_ms": 0.0,
+               "t_small_ms": 0.0, "t_lift_ms": 0.0, "rh_iters": 0}
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            info, rc = nk.nk_sign_apply_device(lat.h, params(**kw), x, y)
+            for f in acc:
+                acc[f] = acc[f] + getattr(info, f) if f != "rh_iters" else info.rh_iters
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / nsteps, acc
+
+    # the headline form: nested with learned scaling; warmup, then K timed steps
+    # (kernel durations sampled with HIP events bound to the launches)
     for _ in range(args.warmup):
-        nk.nk_sign_apply_device(lat.h, params(args.k, args.ell), x, y)
+        nk.nk_sign_apply_device(lat.h, params(args.k, args.ell, scaling=LEARNED), x, y)
     torch.cuda.synchronize()
-    t_st = n_st = t_up = n_up = 0.0
+    t0 = time.perf_counter()
+    st = {"t_stencil_ms": 0.0, "n_stencil": 0, "t_update_ms": 0.0, "n_update": 0}
     ph = {"basis": 0.0, "small": 0.0, "lift": 0.0}
     rh_iters = 0
-    t0 = time.perf_counter()
     for _ in range(args.steps):
-        info, rc = nk.nk_sign_apply_device(lat.h, params(args.k, args.ell, profile=PROFILE_EVERY), x, y)
-        t_st += info.t_stencil_ms
-        n_st += info.n_stencil
-        t_up += info.t_update_ms
-        n_up += info.n_update
+        info, rc = nk.nk_sign_apply_device(lat.h, params(args.k, args.ell, profile=PROFILE_EVERY, scaling=LEARNED),
+                                           x, y)
+        for f in st:
+            st[f] += getattr(info, f)
         ph["basis"] += info.t_basis_ms
         ph["small"] += info.t_small_ms
         ph["lift"] += info.t_lift_ms
         rh_iters = info.rh_iters
     torch.cuda.synchronize()
     t_nested = (time.perf_counter() - t0) / args.steps
+    t_st, n_st, t_up, n_up = st["t_stencil_ms"], st["n_stencil"], st["t_update_ms"], st["n_update"]
 
-    # plain at the same k (fewer steps: it is timed for the comparison only)
-    nplain = max(1, args.steps // 2)
-    nk.nk_sign_apply_device(lat.h, params(args.k, 0), x, y)
+    # the other forms at the same k, fewer steps (timed for the comparison only)
+    nside = max(1, args.steps // 2)
+    t_plain, info_p = timed(nside, k=args.k, ell=0)
+    t_nested_u, info_u = timed(nside, k=args.k, ell=args.ell)
+    # many sources in lockstep (nested, learned scaling): per-source rate
+    nb = args.batch
+    xb = torch.from_numpy(latgen.random_sources(DIMS, nb, 1).reshape(-1)).to(dev)
+    yb = torch.empty_like(xb)
+    pb = params(args.k, args.ell, scaling=LEARNED, nrhs=nb, block=1)
+    nk.nk_sign_apply_device(lat.h, pb, xb, yb)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain_small = 0.0
-    for _ in range(nplain):
-        info_p, _ = nk.nk_sign_apply_device(lat.h, params(args.k, 0), x, y)
-        plain_small += info_p.t_small_ms
+    for _ in range(nside):
+        info_b, _ = nk.nk_sign_apply_device(lat.h, pb, xb, yb)
     torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / nplain
+    t_batch = (time.perf_counter() - t0) / nside
+    del xb, yb
 
+    ng = nk.nk_stencil_groups(lat.h, nk.NK_PREC_FP64, False)
     V = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3]
     k1_avg_s = (t_st / max(n_st, 1)) / 1e3
     k1_bytes = K1_BYTES_PER_SITE * V
@@ -253,20 +286,31 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": "16^4 lattice, mu=0.3 two-sided Lanczos, m_w=-1, random SU(3) links eps=0.8 seed 0, "
-                        "1 Gaussian source, nested sign at relative accuracy 1e-8",
+                        "1 Gaussian source, nested sign with learned Roberts-Higham scaling at relative "
+                        "accuracy 1e-8",
             "k": args.k,
             "ell": args.ell,
             "eps_nested": eps_nested,
             "eps_plain": eps_plain,
             "reference": f"non-nested k={kref}",
         },
-        "plain": {"value": 1.0 / t_plain, "ms_per_step": t_plain * 1e3, "small_ms": plain_small / nplain},
+        "forms": {
+            "nested_learned": {"applies_per_s": 1.0 / t_nested, "rh_iters": rh_iters},
+            "nested_unscaled": {"applies_per_s": 1.0 / t_nested_u, "rh_iters": info_u["rh_iters"],
+                                "small_ms": info_u["t_small_ms"] / nside},
+            "plain_unscaled": {"applies_per_s": 1.0 / t_plain, "rh_iters": info_p["rh_iters"],
+                               "small_ms": info_p["t_small_ms"] / nside},
+            f"nested_learned_batched_{nb}": {"applies_per_s_per_source": nb / t_batch, "ms_per_batch": t_batch * 1e3,
+                                             "two_pass": info_b.two_pass},
+        },
         "nested_vs_plain_speedup": t_plain / t_nested,
+        "learned_model": os.path.relpath(rh_train.WEIGHTS, ROOT) if have_model else None,
         "phases_ms": {k: v / args.steps for k, v in ph.items()},
         "rh_iters": rh_iters,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_bil1w (fused A v, A^dag w two-sided Lanczos stencil step, FP64)",
+            "kernel": f"k_bil1<double, LinksPlain<double>, {ng}> (fused A v, A^dag w two-sided Lanczos stencil "
+                      f"step, FP64, {ng} direction groups chosen by the autotuner)",
             "sampled": f"HIP events on the kernels of every {PROFILE_EVERY}th outer step of the timed applications",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -523,9 +523,12 @@ static void launch_k1(int ng, const Geom& g, const BasisPlan& bp, const LK& lk, 
 
 // The autotuner: time K1 with 2 and with 4 direction groups on this lattice,
 // precision and recurrence (ten launches of each after two warm-up launches,
-// on scratch coefficients and valid partial sums) and keep the faster.  The
-// choice is made once per handle and reused by every later run, so a
-// second (two-pass) sweep runs the same kernels as the first.
+// on scratch coefficients and valid partial sums).  Two groups are taken only
+// when they are more than 5% faster, so that timing noise between close
+// candidates does not change the kernel (and the rounding of the result)
+// from one process to the next.  The choice is made once per handle and
+// reused by every later run, so a second (two-pass) sweep runs the same
+// kernels as the first.
 template <class R, class LK>
 static int tune_k1(nk_lattice* lat, const BasisPlan& bp, const LK& lk, BasisBuffers& b, hipStream_t st, int* ng_out) {
   const Geom& g = lat->g;
@@ -550,8 +553,7 @@ static int tune_k1(nk_lattice* lat, const BasisPlan& bp, const LK& lk, BasisBuff
   hipEvent_t ev[2];
   NK_HIP(hipEventCreate(&ev[0]));
   NK_HIP(hipEventCreate(&ev[1]));
-  float best = INFINITY;
-  int best_ng = NK_GROUPS;
+  float tms[2] = {0.f, 0.f};  // 4 groups, 2 groups
   for (int ng : {4, 2}) {
     for (int rep = 0; rep < 12; ++rep) {
       if (rep == 2) NK_HIP(hipEventRecord(ev[0], st));
@@ -561,13 +563,9 @@ static int tune_k1(nk_lattice* lat, const BasisPlan& bp, const LK& lk, BasisBuff
     NK_HIP(hipGetLastError());
     NK_HIP(hipEventRecord(ev[1], st));
     NK_HIP(hipEventSynchronize(ev[1]));
-    float ms = 0.f;
-    NK_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-    if (ms < best) {
-      best = ms;
-      best_ng = ng;
-    }
+    NK_HIP(hipEventElapsedTime(&tms[ng == 4 ? 0 : 1], ev[0], ev[1]));
   }
+  const int best_ng = tms[1] < 0.95f * tms[0] ? 2 : 4;
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   *ng_out = best_ng;
