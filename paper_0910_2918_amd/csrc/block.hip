@@ -174,11 +174,7 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
   const int s = (xcd_block() * NSB + sb) * 32 + (lane >> 1);
   const bool live = s < g.V;
   C64 mine[M];
-  {
-    C64 acc[1][12];
-    hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, acc);  // dead lanes hop at site 0
-    xput<NG>(xb, w, gi, lane, acc, mine);
-  }
+  hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, xb, w, lane, mine);  // dead lanes hop at site 0
   __syncthreads();
   const size_t kk = (size_t)src * (a.k + 1);
   const double svj = a.sv[kk + j];

@@ -128,10 +128,19 @@ __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const
   const int s = (xcd_block() * NSB + sb) * 64 + lane;
   const bool live = s < g.V;
   Cx<R> mine[M];
+  hop_group<NG>(g, live ? s : 0, lk, vj, gi, R(1), R(1), xb, w, lane, mine);  // a lane past the end hops at site 0
+  // the site's own operands of the epilogue, loaded before the reduction so
+  // that their latency overlaps it
+  Cx<R> ein[M], eprev[M];
   {
-    Cx<R> acc[1][12];
-    hop_group<NG>(g, live ? s : 0, lk, vj, gi, R(1), R(1), acc);  // a lane past the end hops at site 0
-    xput<NG>(xb, w, gi, lane, acc, mine);
+    int se = live ? s : 0;
+    asm volatile("" : "+v"(se));  // keeps these addresses out of the stencil's registers
+#pragma unroll
+    for (int cl = 0; cl < M; ++cl) {
+      const size_t i = (size_t)(gi * M + cl) * g.V + se;
+      ein[cl] = vj[i];
+      eprev[cl] = j > 0 ? vjm1[i] : mk<R>(0, 0);
+    }
   }
   if (flag) return;
   double red[1] = {pr[0] + pr[1]};
@@ -160,11 +169,11 @@ __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const
       const int cc = gi * M + cl;
       const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
       const size_t i = (size_t)cc * g.V + se;
-      const Cx<R> psi = vj[i];
+      const Cx<R> psi = ein[cl];
       Cx<R> a = diag * psi - R(0.5) * hs;
       if (cc >= 6) a = mk<R>(-a.re, -a.im);
       C64 wv = svj * widen(a);
-      if (j > 0) wv = wv - bs * widen(vjm1[i]);
+      if (j > 0) wv = wv - bs * widen(eprev[cl]);
       const Cx<R> wr = narrow<R>(wv);
       p[i] = wr;
       const C64 wd = widen(wr), pd = widen(psi);
@@ -240,11 +249,7 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
   const int s = (xcd_block() * NSB + sb) * 32 + (lane >> 1);
   const bool live = s < g.V;
   Cx<R> mine[M];
-  {
-    Cx<R> acc[1][12];
-    hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, acc);  // dead lanes hop at site 0
-    xput<NG>(xb, w, gi, lane, acc, mine);
-  }
+  hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, xb, w, lane, mine);  // dead lanes hop at site 0
   if (flag) return;
   double red[4];
 #pragma unroll

@@ -276,51 +276,17 @@ __device__ __forceinline__ void hop_bwd(const Geom& g, int s, const SiteC& sc0, 
 // eight hops of a site are in flight at once, and a workgroup covers NG times
 // fewer sites, so fewer sites are in flight per XCD and the neighbour spinors
 // and links they share are still in the XCD's L2 when the next site asks.
+//
+// No 12-component accumulator lives across the hops of a group: each hop's
+// contribution goes straight to the wave's own LDS slots (the first hop
+// stores, later hops add) and to the M components the wave keeps, so while a
+// hop's link and spinor loads are in flight only those M components are live.
+// The additions happen in the same order as with one accumulator per lane,
+// ((h1 + h2) + h3) + ..., so the result is the same to the last bit.
 
 #ifndef NK_GROUPS
 #define NK_GROUPS 4  // direction groups of the stencil kernels (2 or 4)
 #endif
-
-// hopping sum of direction group gi (wave-uniform) of one field at site s;
-// ef/eb are the forward/backward temporal factors
-template <int NG, class R, class LK>
-__device__ __forceinline__ void hop_group(const Geom& g, int s, const LK& lk, const Cx<R>* in, int gi, R ef, R eb,
-                                          Cx<R> (&acc)[1][12]) {
-  const SiteC x = site_coords(g, s);
-  const Cx<R>* ins[1] = {in};
-  const R one[1] = {R(1)};
-  const R f1[1] = {ef};
-  const R b1[1] = {eb};
-#pragma unroll
-  for (int c = 0; c < 12; ++c) acc[0][c] = mk<R>(0, 0);
-  if (NG == 4) {
-    if (gi == 0) {
-      hop_fwd<0>(g, s, x, lk, ins, one, acc);
-      hop_bwd<0>(g, s, x, lk, ins, one, acc);
-    } else if (gi == 1) {
-      hop_fwd<1>(g, s, x, lk, ins, one, acc);
-      hop_bwd<1>(g, s, x, lk, ins, one, acc);
-    } else if (gi == 2) {
-      hop_fwd<2>(g, s, x, lk, ins, one, acc);
-      hop_bwd<2>(g, s, x, lk, ins, one, acc);
-    } else {
-      hop_fwd<3>(g, s, x, lk, ins, f1, acc);
-      hop_bwd<3>(g, s, x, lk, ins, b1, acc);
-    }
-  } else {
-    if (gi == 0) {
-      hop_fwd<0>(g, s, x, lk, ins, one, acc);
-      hop_bwd<0>(g, s, x, lk, ins, one, acc);
-      hop_fwd<1>(g, s, x, lk, ins, one, acc);
-      hop_bwd<1>(g, s, x, lk, ins, one, acc);
-    } else {
-      hop_fwd<2>(g, s, x, lk, ins, one, acc);
-      hop_bwd<2>(g, s, x, lk, ins, one, acc);
-      hop_fwd<3>(g, s, x, lk, ins, f1, acc);
-      hop_bwd<3>(g, s, x, lk, ins, b1, acc);
-    }
-  }
-}
 
 // LDS exchange of the partial hopping sums of the 4 waves of a workgroup
 template <class R, int NG>
@@ -332,26 +298,80 @@ struct XBuf {
 // slot of component cc in the buffer of group gg: below gg's own range it
 // keeps its index, above it moves down by M
 template <int NG>
-__device__ __forceinline__ int xslot(int cc, int gg) {
+__device__ __forceinline__ constexpr int xslot(int cc, int gg) {
   constexpr int M = 12 / NG;
   return cc < gg * M ? cc : cc - M;
 }
 
-// wave w (group gi) hands the components other groups finish to LDS and keeps
-// its own share in mine[]
-template <int NG, class R>
-__device__ __forceinline__ void xput(XBuf<R, NG>& xb, int w, int gi, int lane, const Cx<R> (&acc)[1][12],
+// hand one hop's contribution acc (all 12 components) of group GI to the
+// exchange: components other groups finish go to the wave's LDS slots, its
+// own M components to mine[]; FIRST stores, otherwise adds
+template <int NG, int GI, bool FIRST, class R>
+__device__ __forceinline__ void xacc(XBuf<R, NG>& xb, int w, int lane, const Cx<R> (&acc)[1][12],
                                      Cx<R> (&mine)[12 / NG]) {
   constexpr int M = 12 / NG;
 #pragma unroll
-  for (int cc = 0; cc < 12; ++cc)
-    if (cc / M != gi) xb.v[w][xslot<NG>(cc, gi)][lane] = acc[0][cc];
+  for (int cc = 0; cc < 12; ++cc) {
+    if (cc / M == GI) {
+      mine[cc - GI * M] = FIRST ? acc[0][cc] : mine[cc - GI * M] + acc[0][cc];
+    } else {
+      Cx<R>& slot = xb.v[w][xslot<NG>(cc, GI)][lane];
+      slot = FIRST ? acc[0][cc] : slot + acc[0][cc];
+    }
+  }
+}
+
+// one hop (forward or backward in direction NU) of group GI, handed to the
+// exchange
+template <bool FWD, int NU, int NG, int GI, bool FIRST, class R, class LK>
+__device__ __forceinline__ void hop_x(const Geom& g, int s, const SiteC& x, const LK& lk, const Cx<R>* in, R tf,
+                                      XBuf<R, NG>& xb, int w, int lane, Cx<R> (&mine)[12 / NG]) {
+  const Cx<R>* ins[1] = {in};
+  const R f1[1] = {NU == 3 ? tf : R(1)};
+  Cx<R> acc[1][12];
 #pragma unroll
-  for (int cl = 0; cl < M; ++cl) {
-    mine[cl] = acc[0][cl];
-#pragma unroll
-    for (int gg = 1; gg < NG; ++gg)
-      if (gi == gg) mine[cl] = acc[0][gg * M + cl];
+  for (int c = 0; c < 12; ++c) acc[0][c] = mk<R>(0, 0);
+  if constexpr (FWD)
+    hop_fwd<NU>(g, s, x, lk, ins, f1, acc);
+  else
+    hop_bwd<NU>(g, s, x, lk, ins, f1, acc);
+  xacc<NG, GI, FIRST>(xb, w, lane, acc, mine);
+}
+
+// hopping sum of direction group gi (wave-uniform) of one field at site s,
+// left in the exchange (LDS slots of wave w and mine[]); ef/eb are the
+// forward/backward temporal factors
+template <int NG, class R, class LK>
+__device__ __forceinline__ void hop_group(const Geom& g, int s, const LK& lk, const Cx<R>* in, int gi, R ef, R eb,
+                                          XBuf<R, NG>& xb, int w, int lane, Cx<R> (&mine)[12 / NG]) {
+  const SiteC x = site_coords(g, s);
+  if constexpr (NG == 4) {
+    if (gi == 0) {
+      hop_x<true, 0, 4, 0, true>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 0, 4, 0, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+    } else if (gi == 1) {
+      hop_x<true, 1, 4, 1, true>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 1, 4, 1, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+    } else if (gi == 2) {
+      hop_x<true, 2, 4, 2, true>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 2, 4, 2, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+    } else {
+      hop_x<true, 3, 4, 3, true>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 3, 4, 3, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+    }
+  } else {
+    static_assert(NG == 2, "2 or 4 direction groups");
+    if (gi == 0) {
+      hop_x<true, 0, 2, 0, true>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 0, 2, 0, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+      hop_x<true, 1, 2, 0, false>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 1, 2, 0, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+    } else {
+      hop_x<true, 2, 2, 1, true>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 2, 2, 1, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+      hop_x<true, 3, 2, 1, false>(g, s, x, lk, in, ef, xb, w, lane, mine);
+      hop_x<false, 3, 2, 1, false>(g, s, x, lk, in, eb, xb, w, lane, mine);
+    }
   }
 }
 

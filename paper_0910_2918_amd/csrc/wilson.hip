@@ -25,11 +25,7 @@ __global__ void __launch_bounds__(256) k_apply(Geom g, LK lk, R diag, int g5, Fi
   const int s = (xcd_block() * NSB + sb) * SPW + lane / NF;
   const bool live = s < g.V;
   Cx<R> mine[M];
-  {
-    Cx<R> acc[1][12];
-    hop_group<NG>(g, live ? s : 0, lk, x, gi, ef, eb, acc);  // a lane past the end hops at site 0
-    xput<NG>(xb, w, gi, lane, acc, mine);
-  }
+  hop_group<NG>(g, live ? s : 0, lk, x, gi, ef, eb, xb, w, lane, mine);  // a lane past the end hops at site 0
   __syncthreads();
   if (!live) return;
   int se = s;
