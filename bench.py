@@ -44,6 +44,36 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_PMC = os.path.join(ROOT, "profiles", "k_bil1_16x16x16x16_pmc.json")
 
 
+def step_kernel_bytes(hermitian: bool, prec: int) -> tuple:
+    """Algorithmic bytes per site of the two kernels of one outer step: links
+    read once, every vector read or written once (FP64 / FP32 spinors of 12
+    complex entries; FP64, FP32 or BF16 two-row links)."""
+    spinor = 12 * (16 if prec == 0 else 8)
+    links = {0: 4 * 9 * 16, 1: 4 * 9 * 8, 2: 4 * 6 * 4}[prec]
+    if hermitian:  # K1: v_j, v_{j-1} in, p out; K2: p, v_j in, v_{j+1} out
+        return links + 3 * spinor, 3 * spinor
+    # K1: v_j, w_j, v_{j-1}, w_{j-1} in, p, q out; K2: p, q, v_j, w_j in, v_{j+1}, w_{j+1} out
+    return links + 6 * spinor, 6 * spinor
+
+
+def copy_rate(torch, dev) -> float:
+    """GB/s of a plain device copy of 1 GiB (read 1 GiB, write 1 GiB): larger
+    than the Infinity Cache, so it shows what streaming from HBM reaches."""
+    n = 1024 * 1024 * 1024 // 16
+    src = torch.ones(n, dtype=torch.complex128, device=dev)
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = float("inf")
+    for _ in range(4):
+        ev[0].record()
+        torch.mul(src, 2.0, out=dst)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    del src, dst
+    return 2 * n * 16 / (best / 1e3) / 1e9
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("krylov.hip", "stencil.h", "nk_internal.h"):
@@ -262,6 +292,53 @@ def main() -> int:
 
     ng = nk.nk_stencil_groups(lat.h, nk.NK_PREC_FP64, False)
     V = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3]
+
+    # the two kernels of an outer step in every precision and recurrence:
+    # HIP events on every launch of a short plain run (k = 60) on the same
+    # lattice, after one untimed run (which also tunes the kernel)
+    copy_gbs = copy_rate(torch, dev)
+    step_kernels = {}
+    for prec, pname in ((nk.NK_PREC_FP64, "fp64"), (nk.NK_PREC_FP32, "fp32"),
+                        (nk.NK_PREC_FP32_BF16LINKS, "fp32_bf16links")):
+        for mu, rname in ((MU, "two_sided"), (0.0, "lanczos")):
+            pk = nk.nk_sign_params_default(k=60, ell=0, mu=mu, m_w=M_W, precision=prec, profile=1)
+            nk.nk_sign_apply_device(lat.h, pk, x, y)
+            info_k, _ = nk.nk_sign_apply_device(lat.h, pk, x, y)
+            b1, b2 = step_kernel_bytes(mu == 0.0, prec)
+            u1 = info_k.t_stencil_ms / max(info_k.n_stencil, 1) * 1e3
+            u2 = info_k.t_update_ms / max(info_k.n_update, 1) * 1e3
+            step_kernels[f"{pname}_{rname}"] = {
+                "groups": nk.nk_stencil_groups(lat.h, prec, mu == 0.0),
+                "k1_us": u1, "k1_bytes_per_site": b1, "k1_GBps": b1 * V / u1 / 1e3,
+                "k2_us": u2, "k2_bytes_per_site": b2, "k2_GBps": b2 * V / u2 / 1e3,
+            }
+    for v in step_kernels.values():
+        v["k1_frac_of_copy"] = v["k1_GBps"] / copy_gbs
+        v["k1_frac_of_peak"] = v["k1_GBps"] / HBM_PEAK_GBS
+
+    # the block stencil step: 32 sources in lockstep at 16^3 x 32 (plain,
+    # k = 40), per source, beside the one-source kernel on the same lattice
+    bdims, nsrc = (16, 16, 16, 32), 32
+    Vb = bdims[0] * bdims[1] * bdims[2] * bdims[3]
+    with nk.Lattice(bdims) as blat:
+        nk.nk_gauge_set(blat.h, latgen.random_gauge(bdims, EPS, 0))
+        xs = torch.from_numpy(latgen.random_sources(bdims, nsrc, 3).reshape(-1)).to(dev)
+        ys = torch.empty_like(xs)
+        p1 = nk.nk_sign_params_default(k=40, ell=0, mu=MU, m_w=M_W, profile=1)
+        nk.nk_sign_apply_device(blat.h, p1, xs[:12 * Vb], ys[:12 * Vb])
+        i1, _ = nk.nk_sign_apply_device(blat.h, p1, xs[:12 * Vb], ys[:12 * Vb])
+        pbk = nk.nk_sign_params_default(k=40, ell=0, mu=MU, m_w=M_W, profile=1, nrhs=nsrc, block=1)
+        nk.nk_sign_apply_device(blat.h, pbk, xs, ys)
+        ibk, _ = nk.nk_sign_apply_device(blat.h, pbk, xs, ys)
+        del xs, ys
+    one_us = i1.t_stencil_ms / max(i1.n_stencil, 1) * 1e3
+    blk_us = ibk.t_stencil_ms / max(ibk.n_stencil, 1) * 1e3 / nsrc
+    block_stencil = {
+        "lattice": "16^3x32", "sources": nsrc, "k": 40,
+        "k1_us_per_source": blk_us, "k1_GBps_per_source": K1_BYTES_PER_SITE * Vb / blk_us / 1e3,
+        "one_source_k1_us": one_us, "one_source_k1_GBps": K1_BYTES_PER_SITE * Vb / one_us / 1e3,
+        "k2_us_per_source": ibk.t_update_ms / max(ibk.n_update, 1) * 1e3 / nsrc,
+    }
     k1_avg_s = (t_st / max(n_st, 1)) / 1e3
     k1_bytes = K1_BYTES_PER_SITE * V
     achieved = k1_bytes / k1_avg_s / 1e9
@@ -322,6 +399,9 @@ def main() -> int:
             "bytes_per_launch": k1_bytes,
         },
         "update_kernel": {"avg_launch_us": (t_up / max(n_up, 1)) * 1e3, "launches": int(n_up)},
+        "copy_GBps": copy_gbs,
+        "step_kernels": step_kernels,
+        "block_stencil": block_stencil,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.k, args.ell, args.cpu_sample_steps)

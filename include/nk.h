@@ -120,7 +120,9 @@ typedef struct nk_sign_info {
   double rh_residual;     /* |S (S e_1) - e_1| of the final Roberts-Higham iterate S (0 if sgn^2 = 1 holds on e_1) */
   double t_basis_ms, t_small_ms, t_lift_ms;
   /* with params.profile: summed durations and launch counts of the two
-   * outer-recurrence kernels (K1: stencil step, K2: update step) */
+   * outer-recurrence kernels (K1: stencil step, K2: update step); with
+   * params.block = 1 each launch covers all sources of a lockstep range
+   * (block = 2 replays graphs, which carry no events) */
   double t_stencil_ms, t_update_ms;
   int32_t n_stencil, n_update;
 } nk_sign_info;

@@ -17,6 +17,8 @@
 // would cut the occupancy of the stencil kernel in half.  Every reduction
 // is deterministic, so a second sweep over the same data (two-pass lift)
 // reproduces the first bit for bit.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -334,20 +336,33 @@ int nb_elem_b(size_t n) {
   return (int)std::min<size_t>(nb, 512);
 }
 
-// one sweep of the basis for every source: steps 0 .. kmax - 1
-int sweep(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int kmax, hipStream_t st) {
+// one sweep of the basis for every source: steps 0 .. kmax - 1; with
+// profile = n > 0 the stencil and update launches of every n-th step carry
+// HIP events (collected by prof_collect)
+int sweep(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int kmax, int profile, hipStream_t st) {
   const Geom& g = lat->g;
   const LinksPlain<double> lk{lat->U64.as<C64>(), g.V};
   hipLaunchKernelGGL(k_bstart, dim3(a.nb2, a.r), dim3(BT), 0, st, a);
   hipLaunchKernelGGL(k_bred2, dim3(a.r), dim3(BT), 0, st, a, 0);
   const double eft = exp(mu), ebt = exp(-mu);
   for (int j = 0; j < kmax; ++j) {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    const bool timed = profile > 0 && j % profile == 0;
+    if (timed)
+      for (auto& e : ev)
+        if (int r = prof_event(lat, &e)) return r;
     if (ng == 2)
-      hipLaunchKernelGGL(k_blk1<2>, dim3(a.nb1, a.r), dim3(BT), 0, st, g, lk, 4.0 + m_w, eft, ebt, j, a);
+      hipExtLaunchKernelGGL(k_blk1<2>, dim3(a.nb1, a.r), dim3(BT), 0, st, ev[0], ev[1], 0, g, lk, 4.0 + m_w, eft,
+                            ebt, j, a);
     else
-      hipLaunchKernelGGL(k_blk1<4>, dim3(a.nb1, a.r), dim3(BT), 0, st, g, lk, 4.0 + m_w, eft, ebt, j, a);
+      hipExtLaunchKernelGGL(k_blk1<4>, dim3(a.nb1, a.r), dim3(BT), 0, st, ev[0], ev[1], 0, g, lk, 4.0 + m_w, eft,
+                            ebt, j, a);
     hipLaunchKernelGGL(k_bred1, dim3(a.r), dim3(BT), 0, st, a, j);
-    hipLaunchKernelGGL(k_blk2, dim3(a.nb2, a.r), dim3(BT), 0, st, a, j);
+    hipExtLaunchKernelGGL(k_blk2, dim3(a.nb2, a.r), dim3(BT), 0, st, ev[2], ev[3], 0, a, j);
+    if (timed) {
+      lat->evkind.push_back(0);
+      lat->evkind.push_back(1);
+    }
     if (j + 1 < kmax) hipLaunchKernelGGL(k_bred2, dim3(a.r), dim3(BT), 0, st, a, j + 1);
   }
   NK_HIP(hipGetLastError());
@@ -376,7 +391,7 @@ int sweep_graph(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, 
     if (!lat->cap_stream) NK_HIP(hipStreamCreateWithFlags(&lat->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     NK_HIP(hipStreamBeginCapture(lat->cap_stream, hipStreamCaptureModeRelaxed));
-    const int e = sweep(lat, a, ng, m_w, mu, kmax, lat->cap_stream);
+    const int e = sweep(lat, a, ng, m_w, mu, kmax, 0, lat->cap_stream);
     const hipError_t ec = hipStreamEndCapture(lat->cap_stream, &graph);
     if (e) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -483,9 +498,12 @@ static int block_range(nk_lattice* lat, const nk_sign_params* p, const int* ell,
   NK_HIP(hipMemsetAsync(a.flags, 0, r * sizeof(int), st));
   NK_HIP(hipMemsetAsync(a.beta, 0, (size_t)r * k * sizeof(C64), st));
   NK_HIP(hipMemsetAsync(a.delta, 0, (size_t)r * k * sizeof(C64), st));
+  // (graph replays carry no events: profiling times the direct launches)
+  lat->evkind.clear();
+  lat->evnext = 0;
   auto run_sweep = [&](const BArgs& args, int kmax) {
     return p->block == 2 ? sweep_graph(lat, args, ng, p->m_w, p->mu, kmax, st)
-                         : sweep(lat, args, ng, p->m_w, p->mu, kmax, st);
+                         : sweep(lat, args, ng, p->m_w, p->mu, kmax, p->profile, st);
   };
   if (int e = run_sweep(a, k)) return e;
   NK_HIP(hipEventRecord(ev[1], st));
@@ -584,6 +602,17 @@ static int block_range(nk_lattice* lat, const nk_sign_params* p, const int* ell,
     info->t_basis_ms = t0;
     info->t_small_ms = t1;
     info->t_lift_ms = t2;
+  }
+  if (p->profile) {  // per launch: each covers all r sources of this range
+    double a1 = 0, a2 = 0;
+    int n1 = 0, n2 = 0;
+    if (int e = prof_collect(lat, &a1, &a2, &n1, &n2)) return e;
+    if (info) {
+      info->t_stencil_ms += a1;
+      info->t_update_ms += a2;
+      info->n_stencil += n1;
+      info->n_update += n2;
+    }
   }
   return warn;
 }

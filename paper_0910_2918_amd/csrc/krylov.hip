@@ -41,21 +41,33 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
   for (int q = 0; q < NQ; ++q) v[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
 }
 
-// sum of nb partial sums per quantity, the same value in every thread; the
-// loads go out eight at a time so that long partial arrays cost one or two
-// L2 round trips, not one per element
+// two consecutive partial sums (b, b + 1) of an array of nb in one 16-byte
+// load, 0 for b >= nb.  Partial arrays have an even count per quantity
+// (every producer launches an even number of workgroups), so pairs never
+// straddle two quantities.  The load itself is unconditional (pair 0 stands
+// in past the end), so a batch of them is issued back to back instead of one
+// branch and one wait per load.
+__device__ __forceinline__ double pair_sum(const double* __restrict__ part, int b, int nb) {
+  const bool in = b < nb;
+  const double2 t = *reinterpret_cast<const double2*>(part + (in ? b : 0));
+  return in ? t.x + t.y : 0.0;
+}
+
+// sum of nb (even) partial sums per quantity, the same value in every
+// thread; the loads go out four pairs at a time so that long partial arrays
+// cost one or two L2 round trips, not one per element
 template <int NQ>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, double (&v)[NQ]) {
-  constexpr int B = 8;
+  constexpr int B = 4;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  for (int b0 = threadIdx.x; b0 < nb; b0 += B * NT) {
+  for (int b0 = 2 * threadIdx.x; b0 < nb; b0 += 2 * B * NT) {
     double t[NQ][B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
-      const int b = b0 + u * NT;
+      const int b = b0 + 2 * u * NT;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) t[q][u] = b < nb ? part[q * nb + b] : 0.0;
+      for (int q = 0; q < NQ; ++q) t[q][u] = pair_sum(part + q * nb, b, nb);
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -119,9 +131,8 @@ __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const
   constexpr int NSB = (NT / 64) / NG;  // site blocks of 64 per workgroup
   __shared__ XBuf<R, NG> xb;
   const int flag = c.flags[0];
-  double pr[2];  // this thread's share of the previous partial sums (nbIn <= 2 NT)
-#pragma unroll
-  for (int u = 0; u < 2; ++u) pr[u] = threadIdx.x + u * NT < nbIn ? partIn[threadIdx.x + u * NT] : 0.0;
+  // this thread's pair of the previous partial sums (nbIn <= 2 NT, even)
+  const double pr = pair_sum(partIn, 2 * threadIdx.x, nbIn);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gi = w % NG, sb = w / NG;
@@ -143,7 +154,7 @@ __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const
     }
   }
   if (flag) return;
-  double red[1] = {pr[0] + pr[1]};
+  double red[1] = {pr};
   block_sum<1>(red);  // also completes the exchange
   const double beta = sqrt(red[0]);
   if (!(beta > 0.0) || !(beta < 1e300)) {  // invariant subspace reached (or non-finite input)
@@ -233,14 +244,9 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
   constexpr int NSB = (NT / 64) / NG;  // site blocks of 32 per workgroup
   __shared__ XBuf<R, NG> xb;
   const int flag = c.flags[0];
-  double pr[4][2];  // this thread's share of the previous partial sums (nbIn <= 2 NT)
+  double pr[4];  // this thread's pair of the previous partial sums (nbIn <= 2 NT, even)
 #pragma unroll
-  for (int qd = 0; qd < 4; ++qd)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int bb = threadIdx.x + u * NT;
-      pr[qd][u] = bb < nbIn ? partIn[qd * nbIn + bb] : 0.0;
-    }
+  for (int qd = 0; qd < 4; ++qd) pr[qd] = pair_sum(partIn + qd * nbIn, 2 * threadIdx.x, nbIn);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int gi = w % NG, sb = w / NG;
@@ -253,7 +259,7 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
   if (flag) return;
   double red[4];
 #pragma unroll
-  for (int qd = 0; qd < 4; ++qd) red[qd] = pr[qd][0] + pr[qd][1];
+  for (int qd = 0; qd < 4; ++qd) red[qd] = pr[qd];
   block_sum<4>(red);  // also completes the exchange
   const C64 sdot = mk(red[0], red[1]);
   const double sabs = sqrt(norm2(sdot));
@@ -296,14 +302,16 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
       const int cc = gi * M + cl;
       const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
       const size_t i = (size_t)cc * g.V + se;
-      Cx<R> a = diag * in[i] - R(0.5) * hs;
+      const Cx<R> ini = in[i];
+      const Cx<R> wpair = pair_swap(ini);  // the odd lane's w_j at this site
+      Cx<R> a = diag * ini - R(0.5) * hs;
       if (cc >= 6) a = mk<R>(-a.re, -a.im);
       const C64 ad = widen(a);
       C64 o = cmul(scale, ad);
       if (j > 0) o = o - cmul(sub, widen(prev[i]));
       out[i] = narrow<R>(o);
       if (f == 0) {
-        const C64 t = cmulc(widen(wj[i]), ad);
+        const C64 t = cmulc(widen(wpair), ad);
         dre += t.re;
         dim += t.im;
       }
@@ -430,6 +438,7 @@ size_t basis_vector_bytes(const Geom& g, int prec) {
 static int nb_elem(const Geom& g) {
   const int n = 12 * g.V;
   int nb = (n + NT - 1) / NT;
+  nb += nb & 1;  // even (pairs of partial sums are read as one load)
   return nb < 2 * NT ? nb : 2 * NT;
 }
 
@@ -465,7 +474,7 @@ static int get_buffers(nk_lattice* lat, const BasisPlan& bp, void* vk_ext, Basis
   return NK_OK;
 }
 
-static int prof_event(nk_lattice* lat, hipEvent_t* ev) {
+int prof_event(nk_lattice* lat, hipEvent_t* ev) {
   if (lat->evnext == lat->evpool.size()) {
     hipEvent_t e;
     NK_HIP(hipEventCreate(&e));
@@ -498,7 +507,8 @@ int prof_collect(nk_lattice* lat, double* t_k1, double* t_k2, int* n_k1, int* n_
 // (Lanczos, one lane per site) or of 32 sites (two-sided, two lanes per site)
 static int k1_blocks(const Geom& g, int hermitian, int ng) {
   const int spb = (hermitian ? 64 : 32) * ((NT / 64) / ng);
-  return (g.V + spb - 1) / spb;
+  const int nb = (g.V + spb - 1) / spb;
+  return nb + (nb & 1);  // even (pairs of partial sums are read as one load)
 }
 
 // one K1 launch with NG = ng direction groups

@@ -190,6 +190,9 @@ size_t basis_vector_bytes(const Geom& g, int prec);
 int basis_run(nk_lattice* lat, const BasisPlan& bp, const C64* x_canon, int j0, int j1, Coefs c, void* vk,
               hipStream_t st, int* breakdown_out);
 // sum the recorded kernel durations (after a synchronisation) and reset the record
+// a (start, stop) event of the handle's pool for profiled launches, and the
+// summed durations of the recorded pairs by kind (0 = stencil step, 1 = update)
+int prof_event(nk_lattice* lat, hipEvent_t* ev);
 int prof_collect(nk_lattice* lat, double* t_k1, double* t_k2, int* n_k1, int* n_k2);
 int lift_run(nk_lattice* lat, const BasisPlan& bp, int kused, const C64* z, double xnorm_dummy, Coefs c,
              const void* vk, C64* y_canon, hipStream_t st);

@@ -392,6 +392,20 @@ __device__ __forceinline__ Cx<R> xsum(const XBuf<R, NG>& xb, int sb, int gi, int
   return hs;
 }
 
+// the value held by the other lane of a lane pair (lane ^ 1), by a DPP quad
+// permutation (1, 0, 3, 2); both lanes of the pair must be active
+__device__ __forceinline__ int pair_swap(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ float pair_swap(float x) { return __int_as_float(pair_swap(__float_as_int(x))); }
+__device__ __forceinline__ double pair_swap(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)pair_swap((int)(unsigned)b), hi = (unsigned)pair_swap((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <class R>
+__device__ __forceinline__ Cx<R> pair_swap(Cx<R> z) {
+  return mk<R>(pair_swap(z.re), pair_swap(z.im));
+}
+
 // gamma5 sign of component c = spin*3 + colour
 __device__ __forceinline__ constexpr int g5sign(int c) { return c < 6 ? 1 : -1; }
 

@@ -52,15 +52,20 @@ def test_block_matches_oracle(setup, ells):
 
 
 def test_block_matches_one_at_a_time(setup):
-    """Same method, other reduction order: the two agree to rounding that the
-    recurrence amplifies over k steps, far below the truncation error."""
+    """Same method, other reduction order: the two agree to the rounding that
+    the recurrence amplifies over k steps.  At k = 100 on this lattice the
+    oracle's own result moves by at most ~1e-11 when the source changes by
+    1e-15 (relative), so 1e-9 leaves two orders of magnitude.  (Further out
+    the short recurrences lose biorthogonality on a lattice this small and
+    the same 1e-15 change moves the result by up to 1e-6 at k = 160, l = 30:
+    no reduction order is preferred there.)"""
     lat, u, xs = setup
-    ells = [30, 60, 90, 45]
-    banner("block vs one-at-a-time, r=4 k=160")
-    yb, _, _ = _run(lat, xs, k=160, ell_per_rhs=ells, block=1)
-    ys, _, _ = _run(lat, xs, k=160, ell_per_rhs=ells, block=0)
+    ells = [20, 40, 60, 30]
+    banner("block vs one-at-a-time, r=4 k=100")
+    yb, _, _ = _run(lat, xs, k=100, ell_per_rhs=ells, block=1)
+    ys, _, _ = _run(lat, xs, k=100, ell_per_rhs=ells, block=0)
     for s in range(4):
-        assert rel(yb[s], ys[s]) < 1e-9
+        assert rel(yb[s], ys[s]) < 1e-9, (s, rel(yb[s], ys[s]))
 
 
 def test_block_two_pass_matches_one_pass(setup):
@@ -139,3 +144,18 @@ def test_block_graph_replays_match_direct_launches(setup):
     for rep in range(2):
         yg2, _, _ = _run(lat, xs, k=120, ell_per_rhs=ells, block=2, two_pass=1)
         assert np.array_equal(yg2, yd2), rep
+
+
+def test_block_profile_counts_and_bits(setup):
+    """profile = 1 on the lockstep path: one stencil and one update event pair
+    per step (each launch covers all sources), positive durations, and the
+    same bits as the unprofiled run."""
+    lat, u, xs = setup
+    ells = [20, 45, 80, 33]
+    banner("block profile events")
+    y0, _, _ = _run(lat, xs, k=100, ell_per_rhs=ells, block=1)
+    y1, info, rc = _run(lat, xs, k=100, ell_per_rhs=ells, block=1, profile=1)
+    assert rc == 0
+    assert info.n_stencil == 100 and info.n_update == 100
+    assert info.t_stencil_ms > 0 and info.t_update_ms > 0
+    assert np.array_equal(y0, y1)
