@@ -331,6 +331,33 @@ def main() -> int:
         nk.nk_sign_apply_device(blat.h, pbk, xs, ys)
         ibk, _ = nk.nk_sign_apply_device(blat.h, pbk, xs, ys)
         del xs, ys
+    # the learned scaling away from the data it was trained on: H_l (l = 250)
+    # of the inner projection at 24^4, mu = 0.5, link width 1.0, k = 1200,
+    # for two sources; Roberts-Higham iterations with each scaling and the
+    # largest |S^2 - 1|_F / sqrt(l) of the results
+    ldims, lk, lell, lmu = (24, 24, 24, 24), 1200, 250, 0.5
+    rh24 = {"lattice": "24^4", "mu": lmu, "eps": 1.0, "k": lk, "ell": lell, "sources": 2}
+    mats = []
+    with nk.Lattice(ldims) as llat:
+        nk.nk_gauge_set(llat.h, latgen.random_gauge(ldims, 1.0, 0))
+        lsrc = latgen.random_sources(ldims, 2, 5)
+        for s_ in range(2):
+            xl = torch.from_numpy(np.ascontiguousarray(lsrc[s_]).reshape(-1)).to(dev)
+            al, be, de, info_l, _ = nk.nk_krylov_basis_device(
+                llat.h, nk.nk_sign_params_default(k=lk, mu=lmu, m_w=M_W), xl)
+            kk = info_l.k_used
+            a_, b_, d_, _, _ = nk.nk_inner_matrix(kk, min(lell, kk), False, al[:kk], be[:kk], de[:kk])
+            mats.append(rh_train.tridiag_dense(a_, b_, d_))
+            del xl
+    for name, sc in (("none", nk.NK_RH_NONE), ("det", nk.NK_RH_DET), ("learned", LEARNED)):
+        its, res = [], 0.0
+        for m in mats:
+            out_m, it_m, _ = nk.nk_rh_sign(m[None], scaling=sc)
+            its.append(int(it_m[0]))
+            sq = out_m[0] @ out_m[0]
+            res = max(res, float(np.linalg.norm(sq - np.eye(sq.shape[0])) / np.sqrt(sq.shape[0])))
+        rh24[f"rh_iters_{name}"] = its
+        rh24[f"resid_{name}"] = res
     one_us = i1.t_stencil_ms / max(i1.n_stencil, 1) * 1e3
     blk_us = ibk.t_stencil_ms / max(ibk.n_stencil, 1) * 1e3 / nsrc
     block_stencil = {
@@ -402,6 +429,7 @@ def main() -> int:
         "copy_GBps": copy_gbs,
         "step_kernels": step_kernels,
         "block_stencil": block_stencil,
+        "learned_scaling_24x24x24x24": rh24,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.k, args.ell, args.cpu_sample_steps)
