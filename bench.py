@@ -408,6 +408,7 @@ def main() -> int:
                                              "two_pass": info_b.two_pass},
         },
         "nested_vs_plain_speedup": t_plain / t_nested,
+        "rh_inverse_shape_k": nk.nk_rh_tile_choice(args.k, 1),
         "learned_model": os.path.relpath(rh_train.WEIGHTS, ROOT) if have_model else None,
         "phases_ms": {k: v / args.steps for k, v in ph.items()},
         "rh_iters": rh_iters,

@@ -249,6 +249,21 @@ int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, dou
 int nk_sign_apply_device(nk_lattice* lat, const nk_sign_params* p, const void* x, void* y,
                          nk_sign_info* info, nk_stream_t stream);
 
+/* Launch shape of the blocked Gauss-Jordan inverse inside Roberts-Higham for
+ * matrices of order > 128 (Eq. (4)): panel threads (256, 512 or 1024) x rows
+ * per thread (1, 2 or 4; their product must cover the order) and the update
+ * tile (32 or 64).  The library's autotuner times every feasible shape once
+ * per class of matrix order (multiples of 64) and batch size (1, 2-4, 5-16,
+ * more) and keeps the fastest; no shape changes a bit of the result.
+ * nk_rh_tile_force fixes one shape for every later call where it is feasible
+ * (0, 0, 0: back to the autotuner); NK_EINVAL for a shape that does not
+ * exist.  nk_rh_tile_choice writes {panel width, rows per thread, panel
+ * threads, tile} chosen for order n and batch size `batch` and returns 1, or
+ * writes zeros and returns 0 before the autotuner has chosen; NK_EINVAL for
+ * n < 1, batch < 1 or a NULL shape.  Both are process-wide and thread-safe. */
+int nk_rh_tile_force(int32_t rows_per_thread, int32_t panel_threads, int32_t update_tile);
+int nk_rh_tile_choice(int32_t n, int32_t batch, int32_t shape[4]);
+
 /* Direction groups (2 or 4) of the outer-recurrence stencil kernel that the
  * autotuner chose on this handle for the given precision and recurrence
  * (hermitian != 0: Lanczos), 0 before the first basis run; NK_EINVAL for a

@@ -546,6 +546,24 @@ int nk_stencil_groups(nk_lattice* lat, int32_t precision, int32_t hermitian) {
 
 int nk_rh_model_set(const float* params) { return nk::mlp_model_set(params); }
 
+int nk_rh_tile_force(int32_t rows_per_thread, int32_t panel_threads, int32_t update_tile) {
+  return nk::rh_tile_force(rows_per_thread, panel_threads, update_tile);
+}
+
+int nk_rh_tile_choice(int32_t n, int32_t batch, int32_t shape[4]) {
+  if (n < 1 || batch < 1 || !shape) {
+    set_error("invalid argument to nk_rh_tile_choice");
+    return NK_EINVAL;
+  }
+  int nb = 0, rm = 0, pth = 0, tile = 0;
+  const int have = nk::rh_tile_choice(n, batch, &nb, &rm, &pth, &tile);
+  shape[0] = nb;
+  shape[1] = rm;
+  shape[2] = pth;
+  shape[3] = tile;
+  return have;
+}
+
 int nk_rh_features_device(int32_t batch, int32_t ld, const int32_t* n, const void* S, float* feat,
                           nk_stream_t stream) {
   if (batch < 1 || ld < 1 || !n || !S || !feat) {

@@ -227,6 +227,11 @@ int small_inner_batch(int r, const int* k, const int* ell, int hermitian, const 
 
 // rh.hip -- batched Roberts-Higham on dense matrices (S on the device, row-major,
 // matrix b at b * ld * ld)
+// the blocked inverse's launch shape: force one for every later call (all
+// zero: back to the autotuner), or read the autotuner's choice for a size and
+// batch class (returns 0 before it has chosen)
+int rh_tile_force(int rm, int pth, int tile);
+int rh_tile_choice(int maxn, int batch, int* nb, int* rm, int* pth, int* tile);
 int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
                     int* iters_host, double* resid_host, hipStream_t st);
 

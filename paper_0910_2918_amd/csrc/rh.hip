@@ -11,20 +11,27 @@
 //      new[pos][j] = (pos in panel ? 0 : old[src(pos)][j]) + sum_t M[pos][t] old[src(c0 + t)][j],
 //    reading the previous buffer and writing the other one (ping-pong), so
 //    no workgroup ever reads a row another one is writing.
+// The panel's thread count (and so rows per thread) and the update's tile
+// are chosen per matrix-size class by timing every feasible pair once (the
+// autotuner below); none of them changes the arithmetic: the pivot is the
+// largest candidate with ties to the smaller position whatever the thread
+// count, and every element sums its panel terms in the same order whatever
+// the tile, so the choice never changes a bit of the result.
 // k_rh_combine undoes the accumulated row permutation as a column
 // permutation of the inverse, forms the average (optionally with a positive
 // scale mu, which leaves the limit unchanged) and emits partial sums of
 // |S_{n+1} - S_n|_F^2 and |S_{n+1}|_F^2 for the host's stopping test.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
 
 #include "nk_internal.h"
 
 namespace nk {
 
-constexpr int PT = 1024;  // panel threads
-constexpr int UT = 256;   // update threads, 64 x 64 tile
+constexpr int PT = 1024;  // largest panel thread count
+constexpr int UT = 256;   // update threads (16 x 16), each (T / 16)^2 elements of a T x T tile
 
 __device__ __forceinline__ double cabs1(C64 a) { return fabs(a.re) + fabs(a.im); }
 
@@ -36,8 +43,8 @@ __device__ __forceinline__ C64 cinv(C64 a) {
   return mk(ar / d, -ai / d);
 }
 
-template <int NB, int RM>
-__global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
+template <int NB, int RM, int PTH>
+__global__ void __launch_bounds__(PTH) k_gj_panel(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
                                                  int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
                                                  int* __restrict__ p2r_b, int* __restrict__ perm_b,
                                                  double* __restrict__ logdet, int* __restrict__ sing) {
@@ -51,11 +58,11 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
   int* p2r = p2r_b + (size_t)b * ld;
   int* perm = perm_b + (size_t)b * ld;
 
-  __shared__ int s_p2r[PT * RM];
-  __shared__ int s_r2p[PT * RM];
+  __shared__ int s_p2r[PTH * RM];
+  __shared__ int s_r2p[PTH * RM];
   __shared__ C64 s_prow[NB];
-  __shared__ double s_val[PT / 64];
-  __shared__ int s_pos[PT / 64];
+  __shared__ double s_val[PTH / 64];
+  __shared__ int s_pos[PTH / 64];
   __shared__ double s_ld;
   __shared__ int s_sing;
 
@@ -63,11 +70,11 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
   C64 a[RM][NB];
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
-    const int r = tid + m * PT;
+    const int r = tid + m * PTH;
 #pragma unroll
     for (int t = 0; t < NB; ++t) a[m][t] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
   }
-  for (int r = tid; r < n; r += PT) {
+  for (int r = tid; r < n; r += PTH) {
     s_p2r[r] = r;
     s_r2p[r] = r;
   }
@@ -85,7 +92,7 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
       int bpos = 0x7fffffff;
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const int r = tid + m * PT;
+        const int r = tid + m * PTH;
         if (r < n) {
           const int pos = s_r2p[r];
           const double v = cabs1(a[m][t]);
@@ -112,7 +119,7 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
       best = s_val[0];
       bpos = s_pos[0];
 #pragma unroll
-      for (int w = 1; w < PT / 64; ++w) {
+      for (int w = 1; w < PTH / 64; ++w) {
         const double ov = s_val[w];
         const int op = s_pos[w];
         if (ov > best || (ov == best && op < bpos)) {
@@ -123,10 +130,10 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
       const int p = bpos;
       const int pr = s_p2r[p];
       const int rc = s_p2r[c];
-      if ((pr & (PT - 1)) == tid) {
+      if ((pr & (PTH - 1)) == tid) {
 #pragma unroll
         for (int m = 0; m < RM; ++m) {
-          if (m == pr / PT) {
+          if (m == pr / PTH) {
             const C64 piv = a[m][t];
             if (!(best > 0.0)) s_sing = 1;
             const C64 d = cinv(piv);
@@ -145,7 +152,7 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
       }
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const int r = tid + m * PT;
+        const int r = tid + m * PTH;
         if (r < n) {
           if (r == pr) {
 #pragma unroll
@@ -166,7 +173,7 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
   // M in pivot order, the panel's position -> source-row map, the running permutation
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
-    const int r = tid + m * PT;
+    const int r = tid + m * PTH;
     if (r < n) {
       const int pos = s_r2p[r];
 #pragma unroll
@@ -177,13 +184,13 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
   int pv[RM];
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
-    const int pos = tid + m * PT;
+    const int pos = tid + m * PTH;
     pv[m] = pos < n ? perm[s_p2r[pos]] : 0;
   }
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
-    const int pos = tid + m * PT;
+    const int pos = tid + m * PTH;
     if (pos < n) {
       perm[pos] = pv[m];
       p2r[pos] = s_p2r[pos];
@@ -195,45 +202,46 @@ __global__ void __launch_bounds__(PT) k_gj_panel(int ld, const int* __restrict__
   }
 }
 
-template <int NB>
+template <int NB, int T>
 __global__ void __launch_bounds__(UT) k_gj_update(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
                                                   int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
                                                   const int* __restrict__ p2r_b) {
   const int b = blockIdx.z;
   const int n = nvec[b];
   if (!active[b] || c0 >= n) return;
-  const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
+  constexpr int E = T / 16;  // rows and columns per thread
+  const int row0 = blockIdx.y * T, col0 = blockIdx.x * T;
   if (row0 >= n || col0 >= n) return;
   const int nbe = min(NB, n - c0);
   const size_t off = (size_t)b * ld * ld;
   const C64* Aold = Aold_b + off;
   C64* Anew = Anew_b + off;
   const int* p2r = p2r_b + (size_t)b * ld;
-  __shared__ C64 sM[64][NB + 1];
-  __shared__ C64 sR[NB][64 + 1];
-  __shared__ int sP[64];
+  __shared__ C64 sM[T][NB + 1];
+  __shared__ C64 sR[NB][T + 1];
+  __shared__ int sP[T];
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * NB; e += UT) {
+  for (int e = tid; e < T * NB; e += UT) {
     const int i = e / NB, t = e % NB;
     const int pos = row0 + i;
     sM[i][t] = (pos < n && t < nbe) ? Anew[(size_t)pos * ld + c0 + t] : mk(0.0, 0.0);
   }
-  for (int e = tid; e < 64 * NB; e += UT) {
-    const int t = e / 64, j = e % 64;
+  for (int e = tid; e < T * NB; e += UT) {
+    const int t = e / T, j = e % T;
     const int col = col0 + j;
     sR[t][j] = (t < nbe && col < n) ? Aold[(size_t)p2r[c0 + t] * ld + col] : mk(0.0, 0.0);
   }
-  if (tid < 64) sP[tid] = (row0 + tid < n) ? p2r[row0 + tid] : 0;
+  if (tid < T) sP[tid] = (row0 + tid < n) ? p2r[row0 + tid] : 0;
   __syncthreads();
   const int tx = tid & 15, ty = tid >> 4;
 #pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const int i = ty * 4 + ii;
+  for (int ii = 0; ii < E; ++ii) {
+    const int i = ty * E + ii;
     const int pos = row0 + i;
     if (pos >= n) continue;
     const bool inpanel = pos >= c0 && pos < c0 + nbe;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < E; ++q) {
       const int j = tx + 16 * q;
       const int col = col0 + j;
       if (col >= n || (col >= c0 && col < c0 + nbe)) continue;
@@ -503,22 +511,147 @@ std::mutex g_rh_mu;
 DevBuf g_G0, g_G1, g_int, g_dbl, g_mu, g_sched;
 }  // namespace
 
-template <int NB, int RM>
-static void launch_inverse(int batch, int ld, int maxn, const int* nvec, const int* act, C64* S, C64* G0, C64* G1,
-                           int* p2r, int* perm, double* logdet, int* sing, hipStream_t st, int* nb_out) {
+template <int NB, int RM, int PTH, int T>
+static void launch_inverse(int batch, int ld, int maxn, const int* nvec, const int* act, const C64* S, C64* G0,
+                           C64* G1, int* p2r, int* perm, double* logdet, int* sing, hipStream_t st) {
   const C64* cur = S;
   int which = 0;
-  const int tiles = (maxn + 63) / 64;
+  const int tiles = (maxn + T - 1) / T;
   for (int c0 = 0; c0 < maxn; c0 += NB) {
     C64* nxt = which ? G1 : G0;
-    hipLaunchKernelGGL((k_gj_panel<NB, RM>), dim3(batch), dim3(PT), 0, st, ld, nvec, act, c0, cur, nxt, p2r, perm,
-                       logdet, sing);
-    hipLaunchKernelGGL((k_gj_update<NB>), dim3(tiles, tiles, batch), dim3(UT), 0, st, ld, nvec, act, c0, cur, nxt,
+    hipLaunchKernelGGL((k_gj_panel<NB, RM, PTH>), dim3(batch), dim3(PTH), 0, st, ld, nvec, act, c0, cur, nxt, p2r,
+                       perm, logdet, sing);
+    hipLaunchKernelGGL((k_gj_update<NB, T>), dim3(tiles, tiles, batch), dim3(UT), 0, st, ld, nvec, act, c0, cur, nxt,
                        p2r);
     cur = nxt;
     which ^= 1;
   }
-  *nb_out = NB;
+}
+
+// The launch shapes of the blocked inverse: panel threads x rows per thread
+// (which must cover ld) and the update tile.  The panel width is not among
+// the choices: it sets the grouping of the update sums, 16 up to ld = 1024
+// and 8 above, fixed by ld alone.
+struct GJShape {
+  int nb, rm, pth, tile;
+};
+// every instantiated shape (the panel keeps rm x nb complex values per
+// thread in registers, so rm x nb x 4 VGPRs must fit beside the rest at
+// pth / 256 waves per SIMD; 4 rows of 16 would live in scratch memory)
+#define NK_GJ_SHAPES(X)                                                                                      \
+  X(16, 1, 256, 32) X(16, 1, 256, 64) X(16, 1, 512, 32) X(16, 1, 512, 64) X(16, 1, 1024, 32)                \
+  X(16, 1, 1024, 64) X(16, 2, 256, 32) X(16, 2, 256, 64) X(16, 2, 512, 32) X(16, 2, 512, 64)                \
+  X(8, 2, 1024, 32) X(8, 2, 1024, 64) X(8, 4, 512, 32)                                                      \
+  X(8, 4, 512, 64) X(8, 4, 1024, 32) X(8, 4, 1024, 64)
+#define NK_GJ_ENTRY(NB, RM, PTH, T) {NB, RM, PTH, T},
+constexpr GJShape kGJShapes[] = {NK_GJ_SHAPES(NK_GJ_ENTRY)};
+#undef NK_GJ_ENTRY
+
+static int gj_nb(int ld) { return ld <= PT ? 16 : 8; }
+
+static bool gj_feasible(const GJShape& sh, int ld) {
+  for (const GJShape& k : kGJShapes)
+    if (k.nb == sh.nb && k.rm == sh.rm && k.pth == sh.pth && k.tile == sh.tile)
+      return sh.nb == gj_nb(ld) && sh.pth * sh.rm >= ld;
+  return false;
+}
+
+// one blocked inverse with a shape that gj_feasible accepts for ld
+static void launch_inverse_shape(const GJShape& sh, int batch, int ld, int maxn, const int* nvec, const int* act,
+                                 const C64* S, C64* G0, C64* G1, int* p2r, int* perm, double* logdet, int* sing,
+                                 hipStream_t st) {
+#define NK_GJ_CALL(NB, RM, PTH, T)                                                                            \
+  if (sh.nb == NB && sh.rm == RM && sh.pth == PTH && sh.tile == T)                                            \
+    return launch_inverse<NB, RM, PTH, T>(batch, ld, maxn, nvec, act, S, G0, G1, p2r, perm, logdet, sing, st);
+  NK_GJ_SHAPES(NK_GJ_CALL)
+#undef NK_GJ_CALL
+}
+
+// autotuner state: the chosen shape per (size class, batch class), and an
+// optional forced shape (nk_rh_tile_force)
+std::map<int, GJShape> g_gj_choice;
+GJShape g_gj_force{0, 0, 0, 0};
+
+static int gj_key(int maxn, int batch) {
+  const int bc = batch <= 1 ? 0 : batch <= 4 ? 1 : batch <= 16 ? 2 : 3;
+  return ((maxn + 63) / 64) * 4 + bc;
+}
+
+// the shape for this batch: forced, cached, or found by timing one inverse of
+// the current iterate with every feasible shape (the results are discarded;
+// every shape computes the same bits)
+static int gj_choose(int batch, int ld, int maxn, const int* nvec, const int* act, const C64* S, C64* G0, C64* G1,
+                     int* p2r, int* perm, double* logdet, int* sing, hipStream_t st, GJShape* out) {
+  if (g_gj_force.pth) {
+    const GJShape f{gj_nb(ld), g_gj_force.rm, g_gj_force.pth, g_gj_force.tile};
+    if (gj_feasible(f, ld)) {
+      *out = f;
+      return NK_OK;
+    }
+  }
+  const int key = gj_key(maxn, batch);
+  auto it = g_gj_choice.find(key);
+  if (it != g_gj_choice.end() && gj_feasible(it->second, ld)) {
+    *out = it->second;
+    return NK_OK;
+  }
+  hipEvent_t e0, e1;
+  NK_HIP(hipEventCreate(&e0));
+  NK_HIP(hipEventCreate(&e1));
+  float best = INFINITY;
+  GJShape pick{0, 0, 0, 0};
+  for (const GJShape& sh : kGJShapes) {
+    if (!gj_feasible(sh, ld)) continue;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first run of a shape warms it up
+      hipLaunchKernelGGL(k_rh_start, dim3((maxn + 255) / 256, batch), dim3(256), 0, st, ld, batch, nvec, act, perm,
+                         logdet);
+      NK_HIP(hipEventRecord(e0, st));
+      launch_inverse_shape(sh, batch, ld, maxn, nvec, act, S, G0, G1, p2r, perm, logdet, sing, st);
+      NK_HIP(hipEventRecord(e1, st));
+      NK_HIP(hipEventSynchronize(e1));
+      NK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    }
+    if (ms < best) {
+      best = ms;
+      pick = sh;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  NK_HIP(hipGetLastError());
+  g_gj_choice[key] = pick;
+  *out = pick;
+  return NK_OK;
+}
+
+int rh_tile_force(int rm, int pth, int tile) {
+  std::lock_guard<std::mutex> lock(g_rh_mu);
+  if (rm == 0 && pth == 0 && tile == 0) {
+    g_gj_force = GJShape{0, 0, 0, 0};
+    return NK_OK;
+  }
+  for (const GJShape& k : kGJShapes)
+    if (k.rm == rm && k.pth == pth && k.tile == tile) {
+      g_gj_force = GJShape{0, rm, pth, tile};  // nb follows ld at use
+      return NK_OK;
+    }
+  set_error("no blocked-inverse shape with %d rows per thread, %d panel threads and tile %d", rm, pth, tile);
+  return NK_EINVAL;
+}
+
+int rh_tile_choice(int maxn, int batch, int* nb, int* rm, int* pth, int* tile) {
+  std::lock_guard<std::mutex> lock(g_rh_mu);
+  auto it = g_gj_choice.find(gj_key(maxn, batch));
+  if (it == g_gj_choice.end()) {
+    *nb = *rm = *pth = *tile = 0;
+    return 0;
+  }
+  *nb = it->second.nb;
+  *rm = it->second.rm;
+  *pth = it->second.pth;
+  *tile = it->second.tile;
+  return 1;
 }
 
 int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
@@ -591,6 +724,11 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     act_h[b] = n_host[b] > 0 ? 1 : 0;
     iters_host[b] = 0;
   }
+  NK_HIP(hipMemcpyAsync(act, act_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+  GJShape shape;
+  if (int e = gj_choose(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing, st,
+                        &shape))
+    return e;
   NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
   std::vector<double> prev(batch, INFINITY), part_h((size_t)batch * nbl * 2), mu_h(batch, 1.0);
   std::vector<double> sched_h;
@@ -611,16 +749,9 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     }
     hipLaunchKernelGGL(k_rh_start, dim3((maxn + 255) / 256, batch), dim3(256), 0, st, ld, batch, nvec, act, perm,
                        logdet);
-    int nbw = 16;
-    if (ld <= PT)
-      launch_inverse<16, 1>(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing,
-                            st, &nbw);
-    else if (ld <= 2 * PT)
-      launch_inverse<16, 2>(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing,
-                            st, &nbw);
-    else
-      launch_inverse<8, 4>(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing,
-                           st, &nbw);
+    const int nbw = gj_nb(ld);
+    launch_inverse_shape(shape, batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet,
+                         sing, st);
     const int rs = scaling == NK_RH_LEARNED ? NK_RH_LEARNED : (scaling == NK_RH_DET ? NK_RH_DET : NK_RH_NONE);
     hipLaunchKernelGGL(k_rh_combine, dim3(nbl, batch), dim3(256), 0, st, ld, nbw, nvec, act, g_G0.as<C64>(),
                        g_G1.as<C64>(), S, perm, logdet, rs, mu_dev, part);

@@ -65,6 +65,8 @@ EXPORTS = (
     "nk_sign_apply",
     "nk_sign_apply_device",
     "nk_stencil_groups",
+    "nk_rh_tile_force",
+    "nk_rh_tile_choice",
     "nk_last_error",
     "nk_version",
 )
@@ -163,6 +165,8 @@ def library():
         "nk_sign_apply": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info)]),
         "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
         "nk_stencil_groups": (C.c_int, [vp, i32, i32]),
+        "nk_rh_tile_force": (C.c_int, [i32, i32, i32]),
+        "nk_rh_tile_choice": (C.c_int, [i32, i32, P(i32)]),
         "nk_last_error": (C.c_char_p, []),
         "nk_version": (C.c_char_p, []),
     }
@@ -206,6 +210,18 @@ def _hptr(a: np.ndarray):
 def nk_stencil_groups(h, precision: int = 0, hermitian: bool = False) -> int:
     """Direction groups the autotuner chose for the stencil kernel (0 = not yet tuned)."""
     return _check(library().nk_stencil_groups(h, int(precision), 1 if hermitian else 0))
+
+
+def nk_rh_tile_force(rows_per_thread: int = 0, panel_threads: int = 0, update_tile: int = 0) -> None:
+    """Fix the blocked inverse's launch shape for later Roberts-Higham calls (all 0: autotune)."""
+    _check(library().nk_rh_tile_force(int(rows_per_thread), int(panel_threads), int(update_tile)))
+
+
+def nk_rh_tile_choice(n: int, batch: int = 1):
+    """(panel width, rows per thread, panel threads, tile) the autotuner chose, or None."""
+    shape = (C.c_int32 * 4)()
+    have = _check(library().nk_rh_tile_choice(int(n), int(batch), shape))
+    return tuple(shape) if have else None
 
 
 def nk_last_error() -> str:

@@ -63,6 +63,22 @@ def test_rh_sign_rejects_bad_sizes():
         nk.nk_rh_sign(s, n=[5])
 
 
+def test_rh_tile_force_and_choice_arguments():
+    """Host-side checks of the blocked inverse's shape control (no device work)."""
+    from paper_0910_2918_amd import nk
+
+    with pytest.raises(nk.NKError) as ei:
+        nk.nk_rh_tile_force(3, 512, 64)  # no shape with 3 rows per thread
+    assert ei.value.code == nk.NK_EINVAL
+    with pytest.raises(nk.NKError):
+        nk.nk_rh_tile_force(1, 512, 48)  # no 48 tile
+    nk.nk_rh_tile_force(2, 512, 32)
+    nk.nk_rh_tile_force(0, 0, 0)
+    assert nk.nk_rh_tile_choice(300, 1) is None  # nothing tuned in this process
+    with pytest.raises(nk.NKError):
+        nk.nk_rh_tile_choice(0, 1)
+
+
 def test_small_sign_rejects_ell_above_k():
     import numpy as np
 

@@ -109,3 +109,48 @@ def test_small_sign_ragged_k(ritz):
         z, info, rc = b.nk_small_sign(k, k // 2, herm, Hk.alpha, Hk.beta, Hk.delta)
         zo, _ = N.small_sign(Hk, k // 2, herm)
         assert rel(z, zo) < 1e-10, k
+
+
+# every launch shape of the blocked inverse that covers each order: (rows per
+# thread, panel threads), each with update tiles 32 and 64
+_SHAPES_LE_512 = [(1, 512), (1, 1024), (2, 256), (2, 512)]
+_SHAPES_LE_2048 = [(2, 1024), (4, 512)]
+
+
+@pytest.mark.parametrize("sizes, shapes", [([300, 150, 229, 1], _SHAPES_LE_512),
+                                           ([1100, 700], _SHAPES_LE_2048)])
+def test_rh_every_launch_shape_gives_the_same_bits(sizes, shapes):
+    """The autotuner's choices (panel threads, rows per thread, update tile)
+    change no arithmetic: every shape returns the same bits, which match the
+    oracle's Roberts-Higham iteration."""
+    banner(f"rh launch shapes, sizes {sizes}")
+    b = nk()
+    ld = max(sizes)
+    S = np.zeros((len(sizes), ld, ld), np.complex128)
+    mats = []
+    for i, n in enumerate(sizes):
+        a = _rand_matrix(n, 300 + i, herm=(i % 2 == 1))
+        mats.append(a)
+        S[i, :n, :n] = a
+    ref = None
+    try:
+        for rm, pth in shapes:
+            for tile in (32, 64):
+                b.nk_rh_tile_force(rm, pth, tile)
+                out, it, rc = b.nk_rh_sign(S, n=sizes)
+                if ref is None:
+                    ref = (out, it)
+                    for i, n in enumerate(sizes):
+                        so, ito, _ = R.roberts_higham(mats[i])
+                        assert rel(out[i, :n, :n], so) < 1e-10, i
+                        assert abs(int(it[i]) - ito) <= 1
+                else:
+                    assert np.array_equal(out, ref[0]), (rm, pth, tile)
+                    assert np.array_equal(it, ref[1]), (rm, pth, tile)
+    finally:
+        b.nk_rh_tile_force(0, 0, 0)
+    # back to the autotuner: it picks a shape for this class, same bits again
+    out, it, _ = b.nk_rh_sign(S, n=sizes)
+    assert np.array_equal(out, ref[0])
+    choice = b.nk_rh_tile_choice(ld, len(sizes))
+    assert choice is not None and choice[2] * choice[1] >= ld, choice
