@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
     for (int cl = 0; cl < M; ++cl) {
       const int cc = gi * M + cl;
       const C64 hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
-      const size_t i = (size_t)cc * g.V + se;
+      const size_t i = sidx<double>(g.V, cc, se);
       C64 av = diag * in[i] - 0.5 * hs;
       if (cc >= 6) av = mk(-av.re, -av.im);
       C64 o = cmul(scale, av);

@@ -94,10 +94,12 @@ __global__ void __launch_bounds__(NT) k_start(int n, const C64* __restrict__ x, 
                                               Cx<R>* __restrict__ w0, double* __restrict__ part, LiftAcc lift) {
   double nrm = 0.0;
   const C64 c0 = lift.y ? lift.lc[0] : mk(0.0, 0.0);
+  const int V = n / 12;
   for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-    Cx<R> a = narrow<R>(x[i]);
-    v0[i] = a;
-    if (w0) w0[i] = a;
+    Cx<R> a = narrow<R>(x[i]);  // x and y in the FP64 layout, v0 and w0 in that of R
+    const size_t ir = sidx_of64<R>(V, i);
+    v0[ir] = a;
+    if (w0) w0[ir] = a;
     nrm += norm2(widen(a));
     if (lift.y) lift.y[i] = cmul(c0, widen(a));
   }
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const
     asm volatile("" : "+v"(se));  // keeps these addresses out of the stencil's registers
 #pragma unroll
     for (int cl = 0; cl < M; ++cl) {
-      const size_t i = (size_t)(gi * M + cl) * g.V + se;
+      const size_t i = sidx<R>(g.V, gi * M + cl, se);
       ein[cl] = vj[i];
       eprev[cl] = j > 0 ? vjm1[i] : mk<R>(0, 0);
     }
@@ -179,7 +181,7 @@ __global__ void __launch_bounds__(NT) k_lan1(Geom g, LK lk, R diag, int j, const
     for (int cl = 0; cl < M; ++cl) {
       const int cc = gi * M + cl;
       const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
-      const size_t i = (size_t)cc * g.V + se;
+      const size_t i = sidx<R>(g.V, cc, se);
       const Cx<R> psi = ein[cl];
       Cx<R> a = diag * psi - R(0.5) * hs;
       if (cc >= 6) a = mk<R>(-a.re, -a.im);
@@ -216,7 +218,10 @@ __global__ void __launch_bounds__(NT) k_lan2(int n, int j, const Cx<R>* __restri
     vnext[i] = vr;
     const C64 vd = widen(vr);
     nrm += norm2(vd);
-    if (acc) lift.y[i] = lift.y[i] + cmul(lcn, vd);
+    if (acc) {
+      const size_t iy = sidx_to64<R>(n / 12, i);
+      lift.y[iy] = lift.y[iy] + cmul(lcn, vd);
+    }
   }
   double v[1] = {nrm};
   block_sum<1>(v);
@@ -301,7 +306,7 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
     for (int cl = 0; cl < M; ++cl) {
       const int cc = gi * M + cl;
       const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
-      const size_t i = (size_t)cc * g.V + se;
+      const size_t i = sidx<R>(g.V, cc, se);
       const Cx<R> ini = in[i];
       const Cx<R> wpair = pair_swap(ini);  // the odd lane's w_j at this site
       Cx<R> a = diag * ini - R(0.5) * hs;
@@ -383,7 +388,10 @@ __global__ void __launch_bounds__(NT) k_bil2(int n, int j, const Cx<R>* __restri
         sim += t.im;
         nv += norm2(vd);
         nw += norm2(wd);
-        if (acc) lift.y[i] = lift.y[i] + cmul(lcn, vd);
+        if (acc) {
+          const size_t iy = sidx_to64<R>(n / 12, i);
+          lift.y[iy] = lift.y[iy] + cmul(lcn, vd);
+        }
       }
     }
     if (i0 + U * stride < n) load(i0 + U * stride);
@@ -403,21 +411,22 @@ __global__ void __launch_bounds__(NT) k_bil2(int n, int j, const Cx<R>* __restri
 template <class R>
 __global__ void __launch_bounds__(NT) k_lift(int n, int kused, const Cx<R>* __restrict__ vk, size_t colstride,
                                              const C64* __restrict__ lc, C64* __restrict__ y) {
-  const int i = blockIdx.x * NT + threadIdx.x;
+  const int i = blockIdx.x * NT + threadIdx.x;  // y in the FP64 layout, the columns in that of R
   if (i >= n) return;
+  const size_t ir = sidx_of64<R>(n / 12, i);
   C64 a0 = mk(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
   int j = 0;
   for (; j + 4 <= kused; j += 4) {
-    const Cx<R> v0 = vk[(size_t)(j + 0) * colstride + i];
-    const Cx<R> v1 = vk[(size_t)(j + 1) * colstride + i];
-    const Cx<R> v2 = vk[(size_t)(j + 2) * colstride + i];
-    const Cx<R> v3 = vk[(size_t)(j + 3) * colstride + i];
+    const Cx<R> v0 = vk[(size_t)(j + 0) * colstride + ir];
+    const Cx<R> v1 = vk[(size_t)(j + 1) * colstride + ir];
+    const Cx<R> v2 = vk[(size_t)(j + 2) * colstride + ir];
+    const Cx<R> v3 = vk[(size_t)(j + 3) * colstride + ir];
     a0 = a0 + cmul(lc[j + 0], widen(v0));
     a1 = a1 + cmul(lc[j + 1], widen(v1));
     a2 = a2 + cmul(lc[j + 2], widen(v2));
     a3 = a3 + cmul(lc[j + 3], widen(v3));
   }
-  for (; j < kused; ++j) a0 = a0 + cmul(lc[j], widen(vk[(size_t)j * colstride + i]));
+  for (; j < kused; ++j) a0 = a0 + cmul(lc[j], widen(vk[(size_t)j * colstride + ir]));
   y[i] = (a0 + a1) + (a2 + a3);
 }
 

@@ -21,7 +21,8 @@ __device__ __forceinline__ int dev_site(const Geom& g, int s) {
   return tiled_index(g, x, y, z, t);
 }
 
-// canonical U[site][nu][a][b] -> U64/U32 [(nu*9 + a*3 + b) * V + dsite], Ubf [(nu*6 + e) * V + dsite]
+// canonical U[site][nu][a][b] -> the three device link layouts (FP64, FP32
+// in entry pairs, BF16 rows 0 and 1 as 4 + 2 packed words)
 __global__ void k_pack_gauge(Geom g, const C64* __restrict__ canon, C64* __restrict__ u64, C32* __restrict__ u32,
                              uint32_t* __restrict__ ubf) {
   const int V = g.V;
@@ -32,9 +33,12 @@ __global__ void k_pack_gauge(Geom g, const C64* __restrict__ canon, C64* __restr
     for (int e = 0; e < 9; ++e) {
       C64 v = canon[(size_t)sc * 36 + nu * 9 + e];
       u64[(size_t)(nu * 9 + e) * V + s] = v;
-      u32[(size_t)(nu * 9 + e) * V + s] = narrow<float>(v);
-      if (e < 6) ubf[(size_t)(nu * 6 + e) * V + s] = f2bf16((float)v.re) | (f2bf16((float)v.im) << 16);
+      u32[((size_t)(nu * 5 + e / 2) * V + s) * 2 + (e & 1)] = narrow<float>(v);
+      const uint32_t w = f2bf16((float)v.re) | (f2bf16((float)v.im) << 16);
+      if (e < 4) ubf[((size_t)nu * V + s) * 4 + e] = w;
+      else if (e < 6) ubf[(size_t)16 * V + ((size_t)nu * V + s) * 2 + (e - 4)] = w;
     }
+    u32[((size_t)(nu * 5 + 4) * V + s) * 2 + 1] = mk(0.f, 0.f);  // unused half of entry 8's pair
   }
 }
 
@@ -44,7 +48,7 @@ __global__ void k_pack_spinor(Geom g, const C64* __restrict__ canon, Cx<R>* __re
   if (sc >= g.V) return;
   const int s = dev_site(g, sc);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) dev[(size_t)c * g.V + s] = narrow<R>(canon[(size_t)sc * 12 + c]);
+  for (int c = 0; c < 12; ++c) dev[sidx<R>(g.V, c, s)] = narrow<R>(canon[(size_t)sc * 12 + c]);
 }
 
 template <class R>
@@ -53,7 +57,7 @@ __global__ void k_unpack_spinor(Geom g, const Cx<R>* __restrict__ dev, C64* __re
   if (sc >= g.V) return;
   const int s = dev_site(g, sc);
 #pragma unroll
-  for (int c = 0; c < 12; ++c) canon[(size_t)sc * 12 + c] = widen(dev[(size_t)c * g.V + s]);
+  for (int c = 0; c < 12; ++c) canon[(size_t)sc * 12 + c] = widen(dev[sidx<R>(g.V, c, s)]);
 }
 
 void geom_init(Geom& g, const int dims[4]) {
@@ -84,7 +88,7 @@ void geom_init(Geom& g, const int dims[4]) {
 
 int pack_gauge(nk_lattice* lat, const C64* canon, hipStream_t st) {
   const int V = lat->g.V;
-  if (lat->U64.ensure((size_t)36 * V * sizeof(C64)) || lat->U32.ensure((size_t)36 * V * sizeof(C32)) ||
+  if (lat->U64.ensure((size_t)36 * V * sizeof(C64)) || lat->U32.ensure((size_t)40 * V * sizeof(C32)) ||
       lat->Ubf.ensure((size_t)24 * V * sizeof(uint32_t)))
     return NK_ENOMEM;
   hipLaunchKernelGGL(k_pack_gauge, dim3((V + 255) / 256), dim3(256), 0, st, lat->g, canon, lat->U64.as<C64>(),

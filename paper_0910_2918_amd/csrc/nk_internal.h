@@ -89,11 +89,47 @@ __host__ __device__ __forceinline__ int tiled_index(const Geom& g, int x, int y,
   return (tile << g.lts) + loc;
 }
 
-// device spinor layout: component c = spin*3 + colour is a contiguous array
-// of V complex numbers: field[c * V + site] (tiled site order).  Krylov
-// vectors live in this layout; only pack/unpack see the canonical order.
-// device link layout: U[(nu * 9 + a * 3 + b) * V + site] (FP64 / FP32), or
-// for BF16 storage Ub[(nu * 6 + e) * V + site], e = the 6 complex entries of rows 0, 1.
+// device spinor layout (tiled site order; only pack/unpack see the canonical
+// order).  FP64: component c = spin*3 + colour is a contiguous array of V
+// complex numbers, field[c * V + site].  FP32: components 2p and 2p + 1 of a
+// site sit side by side, field[(p * V + site) * 2 + (c & 1)], so that one
+// 16-byte load fetches two components (one 16-byte FP64 component per load
+// already fills a lane's widest load).  Krylov vectors live in these layouts.
+// Device link layout: FP64 U[(nu * 9 + a * 3 + b) * V + site]; FP32 entries
+// in pairs like the spinors, U[((nu * 5 + e / 2) * V + site) * 2 + (e & 1)]
+// (the pair of entry 8 has an unused second half); BF16 storage keeps the 6
+// complex entries of rows 0, 1 as packed words, words 0-3 of link (nu, site)
+// at [(nu * V + site) * 4 + w] and words 4-5 at [16 V + (nu * V + site) * 2 + w - 4].
+template <class R>
+struct SpinorIndex;
+template <>
+struct SpinorIndex<double> {
+  __host__ __device__ static size_t at(int V, int c, int s) { return (size_t)c * V + s; }
+  __host__ __device__ static size_t to64(int, size_t i) { return i; }
+};
+template <>
+struct SpinorIndex<float> {
+  __host__ __device__ static size_t at(int V, int c, int s) { return ((size_t)(c >> 1) * V + s) * 2 + (c & 1); }
+  // the FP64-layout index of element i of an FP32 vector
+  __host__ __device__ static size_t to64(int V, size_t i) {
+    const size_t ps = i >> 1;
+    return (size_t)(2 * (int)(ps / V) + (int)(i & 1)) * V + (ps % V);
+  }
+};
+// index of component c of device site s in a vector of precision R
+template <class R>
+__host__ __device__ __forceinline__ size_t sidx(int V, int c, int s) {
+  return SpinorIndex<R>::at(V, c, s);
+}
+// index in a vector of precision R of element i of an FP64 vector, and back
+template <class R>
+__host__ __device__ __forceinline__ size_t sidx_of64(int V, size_t i) {
+  return SpinorIndex<R>::at(V, (int)(i / V), (int)(i % V));
+}
+template <class R>
+__host__ __device__ __forceinline__ size_t sidx_to64(int V, size_t i) {
+  return SpinorIndex<R>::to64(V, i);
+}
 
 // ---------------------------------------------------------------------------
 // error state
@@ -167,7 +203,6 @@ int unpack_spinor(const Geom& g, const Cx<R>* dev, C64* canon, hipStream_t st);
 int apply_dw_dev(nk_lattice* lat, double m_w, double mu, int g5, const C64* x, C64* y, hipStream_t st);
 int apply_pair_dev(nk_lattice* lat, double m_w, double mu, const C64* v, const C64* w, C64* av, C64* adw,
                    hipStream_t st);
-int apply_g5dw_any(nk_lattice* lat, int prec, double m_w, double mu, const void* x, void* y, hipStream_t st);
 
 // krylov.hip -- outer basis; coefficient arrays stay on the device
 struct Coefs {

@@ -67,6 +67,7 @@ __device__ __forceinline__ Cx<R> mulu(Cx<R> z) {
 }
 
 // --- link storage -----------------------------------------------------------
+// FP64: one 16-byte load per entry
 template <class R>
 struct LinksPlain {
   const Cx<R>* U;
@@ -77,22 +78,40 @@ struct LinksPlain {
   }
 };
 
+// FP32: entries in pairs, four 16-byte loads and one 8-byte load per link
+template <>
+struct LinksPlain<float> {
+  const Cx<float>* U;
+  int V;
+  __device__ __forceinline__ void load(int nu, int s, Cx<float> (&u)[9]) const {
+    const float4* P = reinterpret_cast<const float4*>(U);
+#pragma unroll
+    for (int pe = 0; pe < 4; ++pe) {
+      const float4 t = P[(size_t)(nu * 5 + pe) * V + s];
+      u[2 * pe] = mk<float>(t.x, t.y);
+      u[2 * pe + 1] = mk<float>(t.z, t.w);
+    }
+    u[8] = U[((size_t)(nu * 5 + 4) * V + s) * 2];
+  }
+};
+
 __device__ __forceinline__ float bf16lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
-// BF16 storage of the first two rows (12 reals as 6 packed complex words);
-// the rows are re-orthonormalised in FP32 and the third row is rebuilt as
-// conj(row0 x row1), which makes the link exactly special unitary again.
+// BF16 storage of the first two rows (12 reals as 6 packed complex words,
+// one 16-byte and one 8-byte load); the rows are re-orthonormalised in FP32
+// and the third row is rebuilt as conj(row0 x row1), which makes the link
+// exactly special unitary again.
 struct LinksBF16 {
   const uint32_t* U;
   int V;
   __device__ __forceinline__ void load(int nu, int s, Cx<float> (&u)[9]) const {
+    const uint4 a = reinterpret_cast<const uint4*>(U)[(size_t)nu * V + s];
+    const uint2 b = reinterpret_cast<const uint2*>(U + (size_t)16 * V)[(size_t)nu * V + s];
+    const uint32_t wv[6] = {a.x, a.y, a.z, a.w, b.x, b.y};
     Cx<float> r[6];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      uint32_t w = U[(size_t)(nu * 6 + e) * V + s];
-      r[e] = mk<float>(bf16lo(w), bf16hi(w));
-    }
+    for (int e = 0; e < 6; ++e) r[e] = mk<float>(bf16lo(wv[e]), bf16hi(wv[e]));
     float n0 = norm2(r[0]) + norm2(r[1]) + norm2(r[2]);
     float i0 = rsqrtf(n0);
 #pragma unroll
@@ -116,6 +135,18 @@ template <class R>
 __device__ __forceinline__ void load_spinor(const Cx<R>* __restrict__ f, int V, int s, Cx<R> (&p)[12]) {
 #pragma unroll
   for (int c = 0; c < 12; ++c) p[c] = f[(size_t)c * V + s];
+}
+// FP32: six 16-byte loads of component pairs
+template <>
+__device__ __forceinline__ void load_spinor<float>(const Cx<float>* __restrict__ f, int V, int s,
+                                                   Cx<float> (&p)[12]) {
+  const float4* P = reinterpret_cast<const float4*>(f);
+#pragma unroll
+  for (int cp = 0; cp < 6; ++cp) {
+    const float4 t = P[(size_t)cp * V + s];
+    p[2 * cp] = mk<float>(t.x, t.y);
+    p[2 * cp + 1] = mk<float>(t.z, t.w);
+  }
 }
 
 // Keep the accumulators materialised at this point of the program: an empty

@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(256) k_apply(Geom g, LK lk, R diag, int g5, Fi
   for (int cl = 0; cl < M; ++cl) {
     const int cc = gi * M + cl;
     const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
-    const size_t i = (size_t)cc * g.V + se;
+    const size_t i = sidx<R>(g.V, cc, se);
     Cx<R> o = diag * x[i] - R(0.5) * hs;
     if (g5 && cc >= 6) o = mk<R>(-o.re, -o.im);
     y[i] = o;
@@ -80,32 +80,6 @@ int apply_pair_dev(nk_lattice* lat, double m_w, double mu, const C64* v, const C
                      st, g, lk, 4.0 + m_w, 1, in, out, tf);
   NK_HIP(hipGetLastError());
   return NK_OK;
-}
-
-// generic entry used by the precision variants and the benchmark paths
-template <class R, class LK>
-int apply_g5dw_prec(const Geom& g, const LK& lk, double m_w, double mu, const Cx<R>* x, Cx<R>* y,
-                    hipStream_t st) {
-  FieldPtrs<R, 1> in{{x}};
-  FieldPtrsW<R, 1> out{{y}};
-  TFac<R, 1> tf{{(R)exp(mu)}, {(R)exp(-mu)}};
-  hipLaunchKernelGGL((k_apply<R, 1, LK, NK_GROUPS>), dim3(apply_blocks(g, 1)), dim3(256), 0, st, g, lk,
-                     (R)(4.0 + m_w), 1, in, out, tf);
-  NK_HIP(hipGetLastError());
-  return NK_OK;
-}
-
-int apply_g5dw_any(nk_lattice* lat, int prec, double m_w, double mu, const void* x, void* y, hipStream_t st) {
-  if (int e = check_gauge(lat)) return e;
-  const Geom& g = lat->g;
-  if (prec == NK_PREC_FP64)
-    return apply_g5dw_prec<double>(g, LinksPlain<double>{lat->U64.as<C64>(), g.V}, m_w, mu, (const C64*)x,
-                                   (C64*)y, st);
-  if (prec == NK_PREC_FP32)
-    return apply_g5dw_prec<float>(g, LinksPlain<float>{lat->U32.as<C32>(), g.V}, m_w, mu, (const C32*)x,
-                                  (C32*)y, st);
-  return apply_g5dw_prec<float>(g, LinksBF16{lat->Ubf.as<uint32_t>(), g.V}, m_w, mu, (const C32*)x, (C32*)y,
-                                st);
 }
 
 }  // namespace nk
