@@ -280,7 +280,7 @@ def main() -> int:
     nb = args.batch
     xb = torch.from_numpy(latgen.random_sources(DIMS, nb, 1).reshape(-1)).to(dev)
     yb = torch.empty_like(xb)
-    pb = params(args.k, args.ell, scaling=LEARNED, nrhs=nb, block=1)
+    pb = params(args.k, args.ell, scaling=LEARNED, nrhs=nb, block=2)
     nk.nk_sign_apply_device(lat.h, pb, xb, yb)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
