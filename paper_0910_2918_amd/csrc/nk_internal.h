@@ -47,6 +47,26 @@ template <class R>
 __host__ __device__ __forceinline__ R norm2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
 
 using C64 = Cx<double>;
+
+// A pointer read from memory (a descriptor in a buffer) or chosen between an
+// LDS and a global array is generic to the compiler, which then emits flat
+// instructions that wait on both the vector-memory and the LDS counters;
+// device buffers are global memory, and this view says so.
+template <class T>
+using gp = T __attribute__((address_space(1)))*;
+template <class T>
+__device__ __forceinline__ gp<T> as_global(T* p) {
+  return (gp<T>)p;
+}
+// complex loads and stores through such a view (struct copies need generic
+// objects; the two halves become one 16-byte access)
+__device__ __forceinline__ Cx<double> ldg(gp<const Cx<double>> p) { return mk<double>(p->re, p->im); }
+__device__ __forceinline__ Cx<double> ldg(gp<Cx<double>> p) { return mk<double>(p->re, p->im); }
+__device__ __forceinline__ Cx<double> ldg(const Cx<double>* p) { return *p; }  // any other space
+__device__ __forceinline__ void stg(gp<Cx<double>> p, Cx<double> v) {
+  p->re = v.re;
+  p->im = v.im;
+}
 using C32 = Cx<float>;
 
 template <class R>

@@ -390,12 +390,15 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
     // a per-iteration copy of the base pointer that the compiler cannot see
     // through: otherwise it hoists SQ 64-bit element addresses out of the
     // iteration loop and keeps them live through every pivot step
-    C64* Si = S;
+    C64* Sp = S;
     int base = r0 * ld + c;  // n <= 128 and ld <= 128: 32-bit offsets suffice
-    asm volatile("" : "+s"(Si), "+v"(base));
+    asm volatile("" : "+s"(Sp), "+v"(base));
+    const gp<C64> Si = as_global(Sp);
 #pragma unroll
     for (int q = 0; q < SQ; ++q) {
-      a[q] = (colok && r0 + q < rend) ? Si[base + q * ld] : mk(0.0, 0.0);
+      C64 v = mk(0.0, 0.0);
+      if (colok && r0 + q < rend) v = ldg(Si + (base + q * ld));
+      a[q] = v;
       if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     for (int r = tid; r < n; r += ST_RH) s_used[r] = 0;

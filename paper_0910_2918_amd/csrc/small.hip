@@ -38,29 +38,18 @@ __device__ __forceinline__ C64 cdiv(C64 a, C64 b) {
 // in LDS by the whole block so the loop does not wait on global memory.
 constexpr int TRI_LDS_MAX = 1365;  // 3 k complex in LDS (<= 64 KB of dynamic LDS)
 
-__global__ void __launch_bounds__(256) k_tri_lu(int k, const C64* __restrict__ alpha, const C64* __restrict__ beta,
-                                                const C64* __restrict__ delta, C64* __restrict__ Lm,
-                                                int* __restrict__ Sw, C64* __restrict__ U0i, C64* __restrict__ U1,
-                                                C64* __restrict__ U2, int* __restrict__ sing) {
-  extern __shared__ C64 sm[];
-  const bool lds = k <= TRI_LDS_MAX;
-  if (lds) {
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-      sm[i] = alpha[i];
-      sm[k + i] = i + 1 < k ? beta[i] : mk(0.0, 0.0);
-      sm[2 * k + i] = i + 1 < k ? delta[i] : mk(0.0, 0.0);
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const C64* al = lds ? sm : alpha;
-  const C64* be = lds ? sm + k : beta;
-  const C64* de = lds ? sm + 2 * k : delta;
+// the sequential elimination, with the coefficients read through al/be/de
+// (LDS or global: one instantiation each, so every access has its own
+// address space)
+template <class P>
+__device__ __forceinline__ void tri_lu_seq(int k, P al, P be, P de, C64* __restrict__ Lm, int* __restrict__ Sw,
+                                           C64* __restrict__ U0i, C64* __restrict__ U1, C64* __restrict__ U2,
+                                           int* __restrict__ sing) {
   const C64 z = mk(0.0, 0.0);
-  C64 a0 = al[0], a1 = k > 1 ? be[0] : z, a2 = z;
+  C64 a0 = ldg(al), a1 = k > 1 ? ldg(be) : z, a2 = z;
   int bad = 0;
   for (int i = 0; i + 1 < k; ++i) {
-    const C64 b0 = de[i], b1 = al[i + 1], b2 = (i + 2 < k) ? be[i + 1] : z;
+    const C64 b0 = ldg(de + i), b1 = ldg(al + i + 1), b2 = (i + 2 < k) ? ldg(be + i + 1) : z;
     const bool sw = cabs1s(a0) < cabs1s(b0);
     const C64 p0 = sw ? b0 : a0, p1 = sw ? b1 : a1, p2 = sw ? b2 : a2;
     const C64 o0 = sw ? a0 : b0, o1 = sw ? a1 : b1, o2 = sw ? a2 : b2;
@@ -84,13 +73,72 @@ __global__ void __launch_bounds__(256) k_tri_lu(int k, const C64* __restrict__ a
   *sing = bad;
 }
 
+__global__ void __launch_bounds__(256) k_tri_lu(int k, const C64* __restrict__ alpha, const C64* __restrict__ beta,
+                                                const C64* __restrict__ delta, C64* __restrict__ Lm,
+                                                int* __restrict__ Sw, C64* __restrict__ U0i, C64* __restrict__ U1,
+                                                C64* __restrict__ U2, int* __restrict__ sing) {
+  extern __shared__ C64 sm[];
+  const bool lds = k <= TRI_LDS_MAX;
+  if (lds) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+      sm[i] = alpha[i];
+      sm[k + i] = i + 1 < k ? beta[i] : mk(0.0, 0.0);
+      sm[2 * k + i] = i + 1 < k ? delta[i] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (lds)
+    tri_lu_seq(k, (const C64*)sm, (const C64*)sm + k, (const C64*)sm + 2 * k, Lm, Sw, U0i, U1, U2, sing);
+  else
+    tri_lu_seq(k, as_global(alpha), as_global(beta), as_global(delta), Lm, Sw, U0i, U1, U2, sing);
+}
+
 // column j of H^{-1} (solve H x = e_j), then B = H + H^{-1}; B row-major k x k.
 // The factors are staged in LDS when they fit.  The forward sweep of e_j is
-// zero before row j - 1, so it starts there.
+// zero before row j - 1, so it starts there.  The backward sweep reads eight
+// rows of the forward result ahead of the recurrence (rows below the one
+// being written, so the reads never see a row of this sweep), which keeps
+// eight loads in flight instead of one.
 struct TriF {
   C64 lm, u0i, u1, u2;
 };
-constexpr int TRI_INV_LDS_MAX = 1024;  // k x 64 B in LDS (<= 64 KB of dynamic LDS)
+constexpr int TRI_INV_LDS_MAX = 960;  // k x (64 + 4) B in LDS (<= 64 KB of dynamic LDS)
+
+template <bool LDS>
+__device__ __forceinline__ void tri_inv_col(int j, int k, const TriF* sf, const int* ssw, gp<const C64> Lm,
+                                            gp<const int> Sw, gp<const C64> U0i, gp<const C64> U1,
+                                            gp<const C64> U2, gp<C64> B) {
+  const C64 z = mk(0.0, 0.0);
+  const int i0 = j > 0 ? j - 1 : 0;
+  for (int i = 0; i < i0; ++i) stg(B + (size_t)i * k + j, z);
+  C64 fc = (j == 0) ? mk(1.0, 0.0) : z;
+  for (int i = i0; i + 1 < k; ++i) {
+    const C64 fn = (i + 1 == j) ? mk(1.0, 0.0) : z;
+    const int sw = LDS ? ssw[i] : Sw[i];
+    const C64 piv = sw ? fn : fc, oth = sw ? fc : fn;
+    stg(B + (size_t)i * k + j, piv);
+    fc = oth - cmul(LDS ? sf[i].lm : ldg(Lm + i), piv);
+  }
+  stg(B + (size_t)(k - 1) * k + j, fc);
+  C64 x1 = z, x2 = z;
+  auto step = [&](int i, C64 y) {
+    const C64 u1 = LDS ? sf[i].u1 : ldg(U1 + i), u2 = LDS ? sf[i].u2 : ldg(U2 + i), u0 = LDS ? sf[i].u0i : ldg(U0i + i);
+    const C64 xi = cmul(y - cmul(u1, x1) - cmul(u2, x2), u0);
+    stg(B + (size_t)i * k + j, xi);
+    x2 = x1;
+    x1 = xi;
+  };
+  int i = k - 1;
+  for (; i >= 7; i -= 8) {
+    C64 y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) y[u] = ldg(B + (size_t)(i - u) * k + j);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) step(i - u, y[u]);
+  }
+  for (; i >= 0; --i) step(i, ldg(B + (size_t)i * k + j));
+}
 
 __global__ void __launch_bounds__(64) k_tri_inv(int k, const C64* __restrict__ Lm, const int* __restrict__ Sw,
                                                 const C64* __restrict__ U0i, const C64* __restrict__ U1,
@@ -98,6 +146,7 @@ __global__ void __launch_bounds__(64) k_tri_inv(int k, const C64* __restrict__ L
                                                 const C64* __restrict__ beta, const C64* __restrict__ delta,
                                                 C64* __restrict__ B) {
   extern __shared__ TriF sf[];
+  int* ssw = reinterpret_cast<int*>(sf + (k <= TRI_INV_LDS_MAX ? k : 0));
   const bool lds = k <= TRI_INV_LDS_MAX;
   if (lds) {
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
@@ -105,32 +154,18 @@ __global__ void __launch_bounds__(64) k_tri_inv(int k, const C64* __restrict__ L
       sf[i].u0i = U0i[i];
       sf[i].u1 = U1[i];
       sf[i].u2 = U2[i];
+      ssw[i] = Sw[i];
     }
     __syncthreads();
   }
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k) return;
-  const C64 z = mk(0.0, 0.0);
-  const int i0 = j > 0 ? j - 1 : 0;
-  for (int i = 0; i < i0; ++i) B[(size_t)i * k + j] = z;
-  C64 fc = (j == 0) ? mk(1.0, 0.0) : z;
-  for (int i = i0; i + 1 < k; ++i) {
-    const C64 fn = (i + 1 == j) ? mk(1.0, 0.0) : z;
-    const int sw = Sw[i];
-    const C64 piv = sw ? fn : fc, oth = sw ? fc : fn;
-    B[(size_t)i * k + j] = piv;
-    fc = oth - cmul(lds ? sf[i].lm : Lm[i], piv);
-  }
-  B[(size_t)(k - 1) * k + j] = fc;
-  C64 x1 = z, x2 = z;
-  for (int i = k - 1; i >= 0; --i) {
-    const C64 y = B[(size_t)i * k + j];
-    const C64 u1 = lds ? sf[i].u1 : U1[i], u2 = lds ? sf[i].u2 : U2[i], u0 = lds ? sf[i].u0i : U0i[i];
-    const C64 xi = cmul(y - cmul(u1, x1) - cmul(u2, x2), u0);
-    B[(size_t)i * k + j] = xi;
-    x2 = x1;
-    x1 = xi;
-  }
+  if (lds)
+    tri_inv_col<true>(j, k, sf, ssw, as_global(Lm), as_global(Sw), as_global(U0i), as_global(U1), as_global(U2),
+                      as_global(B));
+  else
+    tri_inv_col<false>(j, k, sf, ssw, as_global(Lm), as_global(Sw), as_global(U0i), as_global(U1), as_global(U2),
+                       as_global(B));
   B[(size_t)j * k + j] = B[(size_t)j * k + j] + alpha[j];
   if (j > 0) B[(size_t)(j - 1) * k + j] = B[(size_t)(j - 1) * k + j] + beta[j - 1];
   if (j + 1 < k) B[(size_t)(j + 1) * k + j] = B[(size_t)(j + 1) * k + j] + delta[j];
@@ -198,6 +233,40 @@ struct Inner {
   int* flags;
 };
 
+// the descriptor with its buffers seen as global memory (see as_global)
+struct InnerG {
+  int k, herm, lmax, nb1, nb2;
+  gp<const C64> B, BH;
+  gp<C64> V, W, uraw[2], qraw[2], part1, part2, a, b, d;
+  gp<double> part3;
+  gp<int> flags;
+};
+
+__device__ __forceinline__ InnerG inner_view(const Inner& s) {
+  InnerG g;
+  g.k = s.k;
+  g.herm = s.herm;
+  g.lmax = s.lmax;
+  g.nb1 = s.nb1;
+  g.nb2 = s.nb2;
+  g.B = as_global(s.B);
+  g.BH = as_global(s.BH);
+  g.V = as_global(s.V);
+  g.W = as_global(s.W);
+  for (int h = 0; h < 2; ++h) {
+    g.uraw[h] = as_global(s.uraw[h]);
+    g.qraw[h] = as_global(s.qraw[h]);
+  }
+  g.part1 = as_global(s.part1);
+  g.part2 = as_global(s.part2);
+  g.part3 = as_global(s.part3);
+  g.a = as_global(s.a);
+  g.b = as_global(s.b);
+  g.d = as_global(s.d);
+  g.flags = as_global(s.flags);
+  return g;
+}
+
 template <int NTH>
 __device__ __forceinline__ void bsum(double (&v)[4]) {
   __shared__ double sh[4][NTH / 64];
@@ -223,12 +292,12 @@ __device__ __forceinline__ void bsum(double (&v)[4]) {
 // blockIdx.z is SS[blockIdx.z]; the grid is sized for the largest, and a
 // workgroup beyond its own problem's size or steps returns at once.
 __global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ SS, int i) {
-  const Inner& s = SS[blockIdx.z];
+  const InnerG s = inner_view(SS[blockIdx.z]);
   if (i >= s.lmax || (int)blockIdx.x >= s.nb1 || s.flags[0]) return;
   const int k = s.k;
   const int side = blockIdx.y;  // 0: u = B v, 1: q = B^dag w
-  const C64* src = side ? s.qraw[i & 1] : s.uraw[i & 1];
-  C64* dst = side ? s.qraw[(i + 1) & 1] : s.uraw[(i + 1) & 1];
+  gp<const C64> src = side ? s.qraw[i & 1] : s.uraw[i & 1];
+  gp<C64> dst = side ? s.qraw[(i + 1) & 1] : s.uraw[(i + 1) & 1];
   C64 scal = mk(1.0, 0.0), sub = mk(0.0, 0.0);
   C64 scal_o = mk(1.0, 0.0);  // scale of the other side's new column
   if (i > 0) {
@@ -246,8 +315,8 @@ __global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ S
     const double delta = sqrt(sabs);
     const C64 beta = (1.0 / delta) * sd;
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-      s.b[i - 1] = beta;
-      s.d[i - 1] = mk(delta, 0.0);
+      stg(s.b + (i - 1), beta);
+      stg(s.d + (i - 1), mk(delta, 0.0));
     }
     const C64 sv = mk(1.0 / delta, 0.0), sw = (1.0 / norm2(beta)) * beta;  // v = u / delta, w = q / conj(beta)
     scal = side ? sw : sv;
@@ -257,24 +326,40 @@ __global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ S
   __shared__ C64 s_x[GR];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = blockIdx.x * GR + wave;
-  const C64* M = side ? s.BH : s.B;
-  C64* basis = side ? s.W : s.V;
+  gp<const C64> M = side ? s.BH : s.B;
+  gp<C64> basis = side ? s.W : s.V;
   if (r < k) {
-    C64 acc = mk(0.0, 0.0);
-    for (int c = lane; c < k; c += 64) {
-      const C64 xv = (i > 0) ? cmul(scal, src[c]) : mk(c == 0 ? 1.0 : 0.0, 0.0);
-      acc = acc + cmul(M[(size_t)r * k + c], xv);
+    // eight columns per lane and batch, all loads of a batch issued before
+    // the first product (clamped to column 0 past the end)
+    C64 ac[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    for (int c0 = lane; c0 < k; c0 += 8 * 64) {
+      C64 mv[8], xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + 64 * u, cc = c < k ? c : 0;
+        mv[u] = ldg(M + (size_t)r * k + cc);
+        xv[u] = (i > 0) ? ldg(src + cc) : mk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + 64 * u;
+        if (c < k) {
+          const C64 x = (i > 0) ? cmul(scal, xv[u]) : mk(c == 0 ? 1.0 : 0.0, 0.0);
+          ac[u & 3] = ac[u & 3] + cmul(mv[u], x);
+        }
+      }
     }
+    C64 acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       acc.re += __shfl_xor(acc.re, o, 64);
       acc.im += __shfl_xor(acc.im, o, 64);
     }
     if (lane == 0) {
-      const C64 xr = (i > 0) ? cmul(scal, src[r]) : mk(r == 0 ? 1.0 : 0.0, 0.0);
-      basis[(size_t)i * k + r] = xr;
-      if (i > 0) acc = acc - cmul(sub, basis[(size_t)(i - 1) * k + r]);
-      dst[r] = acc;
+      const C64 xr = (i > 0) ? cmul(scal, ldg(src + r)) : mk(r == 0 ? 1.0 : 0.0, 0.0);
+      stg(basis + (size_t)i * k + r, xr);
+      if (i > 0) acc = acc - cmul(sub, ldg(basis + (size_t)(i - 1) * k + r));
+      stg(dst + r, acc);
       s_x[wave] = acc;
     }
   } else if (lane == 0) {
@@ -285,9 +370,9 @@ __global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ S
   // other basis is being written by the other side's blocks in this same
   // launch, so its entries are recomputed here from the raw vector.
   const bool other = !s.herm;
-  const C64* proj = s.herm ? s.V : (side ? s.V : s.W);
-  const C64* osrc = side ? s.uraw[i & 1] : s.qraw[i & 1];
-  C64* out = s.part1 + ((size_t)side * s.nb1 + blockIdx.x) * s.lmax;
+  gp<const C64> proj = s.herm ? s.V : (side ? s.V : s.W);
+  gp<const C64> osrc = side ? s.uraw[i & 1] : s.qraw[i & 1];
+  gp<C64> out = s.part1 + ((size_t)side * s.nb1 + blockIdx.x) * s.lmax;
   for (int j = threadIdx.x; j <= i; j += GR * 64) {
     C64 t = mk(0.0, 0.0);
 #pragma unroll
@@ -295,95 +380,150 @@ __global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ S
       const int rr = blockIdx.x * GR + w;
       if (rr < k) {
         C64 pv;
-        if (j == i && other) pv = (i > 0) ? cmul(scal_o, osrc[rr]) : mk(rr == 0 ? 1.0 : 0.0, 0.0);
-        else pv = proj[(size_t)j * k + rr];
+        if (j == i && other) pv = (i > 0) ? cmul(scal_o, ldg(osrc + rr)) : mk(rr == 0 ? 1.0 : 0.0, 0.0);
+        else pv = ldg(proj + (size_t)j * k + rr);
         t = t + cmulc(pv, s_x[w]);
       }
     }
-    out[j] = t;
+    stg(out + j, t);
   }
 }
 
 // pass 1 (last == 0): reduce part1, subtract, emit part2;
-// pass 2 (last == 1): reduce part2, subtract, emit the normalisation sums
+// pass 2 (last == 1): reduce part2, subtract, emit the normalisation sums.
+// Every phase issues its loads in one batch per thread: the partial-sum and
+// projection phases give each (side, column) four consecutive lanes that
+// split the terms and meet by shuffles; the subtraction handles both sides
+// in the same batch.
+constexpr int TPJ = 4;  // lanes per (side, column) in the reduction phases
+
 __global__ void __launch_bounds__(ST) k_in_sub(const Inner* __restrict__ SS, int i, int last) {
-  const Inner& s = SS[blockIdx.z];
+  const InnerG s = inner_view(SS[blockIdx.z]);
   if (i >= s.lmax || (last && i + 1 >= s.lmax) || (int)blockIdx.x >= s.nb2 || s.flags[0]) return;
   const int k = s.k;
   const int sides = s.herm ? 1 : 2;
   __shared__ C64 s_c[2][LMAX];
   __shared__ C64 s_u[2][SR];
-  const C64* pin = last ? s.part2 : s.part1;
+  gp<const C64> pin = last ? s.part2 : s.part1;
   const int nbin = last ? s.nb2 : s.nb1;
-  for (int side = 0; side < sides; ++side)
-    for (int j = threadIdx.x; j <= i; j += ST) {
-      // four independent partial sums so that the loads overlap (a single
-      // running sum would wait for every load in turn)
-      C64 t0 = mk(0.0, 0.0), t1 = t0, t2 = t0, t3 = t0;
-      const C64* pp = pin + (size_t)side * nbin * s.lmax + j;
-      int bb = 0;
-      for (; bb + 4 <= nbin; bb += 4) {
-        t0 = t0 + pp[(size_t)(bb + 0) * s.lmax];
-        t1 = t1 + pp[(size_t)(bb + 1) * s.lmax];
-        t2 = t2 + pp[(size_t)(bb + 2) * s.lmax];
-        t3 = t3 + pp[(size_t)(bb + 3) * s.lmax];
+  const int ncol = i + 1;
+  const int l4 = threadIdx.x & (TPJ - 1);
+  // reduce the partial projections: item = (side, j), TPJ lanes each
+  for (int it0 = 0; it0 < sides * ncol; it0 += ST / TPJ) {
+    const int item = it0 + (int)threadIdx.x / TPJ;
+    const bool ok = item < sides * ncol;
+    const int side = ok ? item / ncol : 0, j = ok ? item % ncol : 0;
+    gp<const C64> pp = pin + (size_t)side * nbin * s.lmax + j;
+    C64 t0 = mk(0.0, 0.0), t1 = t0;
+    for (int bb0 = l4; bb0 < nbin; bb0 += 8 * TPJ) {
+      C64 pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int bb = bb0 + u * TPJ;
+        pv[u] = ldg(pp + (size_t)(bb < nbin ? bb : 0) * s.lmax);
       }
-      for (; bb < nbin; ++bb) t0 = t0 + pp[(size_t)bb * s.lmax];
-      const C64 t = (t0 + t1) + (t2 + t3);
-      s_c[side][j] = t;
-      if (!last && side == 0 && j == i && blockIdx.x == 0) s.a[i] = s.herm ? mk(t.re, 0.0) : t;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (bb0 + u * TPJ < nbin) {
+          if (u & 1)
+            t1 = t1 + pv[u];
+          else
+            t0 = t0 + pv[u];
+        }
     }
+    C64 t = t0 + t1;
+#pragma unroll
+    for (int o = 1; o < TPJ; o <<= 1) {
+      t.re += __shfl_xor(t.re, o, 64);
+      t.im += __shfl_xor(t.im, o, 64);
+    }
+    if (ok && l4 == 0) {
+      s_c[side][j] = t;
+      if (!last && side == 0 && j == i && blockIdx.x == 0) stg(s.a + i, s.herm ? mk(t.re, 0.0) : t);
+    }
+  }
   __syncthreads();
-  // u -= V c, q -= W d: eight lanes per row
+  // u -= V c, q -= W d: eight lanes per row, columns jl, jl + 8, ... of both
+  // sides in one batch of loads
   const int rl = threadIdx.x >> 3, jl = threadIdx.x & 7;
   const int r = blockIdx.x * SR + rl;
-  C64* u = s.uraw[(i + 1) & 1];
-  C64* q = s.qraw[(i + 1) & 1];
-  for (int side = 0; side < sides; ++side) {
-    const C64* basis = side ? s.W : s.V;
-    C64 acc = mk(0.0, 0.0), acc1 = acc;
-    if (r < k) {
-      int j = jl;
-      for (; j + 8 <= i; j += 16) {
-        acc = acc + cmul(basis[(size_t)j * k + r], s_c[side][j]);
-        acc1 = acc1 + cmul(basis[(size_t)(j + 8) * k + r], s_c[side][j + 8]);
+  gp<C64> u = s.uraw[(i + 1) & 1];
+  gp<C64> q = s.qraw[(i + 1) & 1];
+  C64 acc[2][2] = {{mk(0.0, 0.0), mk(0.0, 0.0)}, {mk(0.0, 0.0), mk(0.0, 0.0)}};
+  if (r < k) {
+    for (int j0 = jl; j0 <= i; j0 += 8 * 8) {
+      C64 bv[2][8];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        gp<const C64> basis = side ? s.W : s.V;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int j = j0 + 8 * m;
+          bv[side][m] = (side < sides) ? ldg(basis + (size_t)(j <= i ? j : 0) * k + r) : mk(0.0, 0.0);
+        }
       }
-      for (; j <= i; j += 8) acc = acc + cmul(basis[(size_t)j * k + r], s_c[side][j]);
+#pragma unroll
+      for (int side = 0; side < 2; ++side)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int j = j0 + 8 * m;
+          if (side < sides && j <= i) acc[side][m & 1] = acc[side][m & 1] + cmul(bv[side][m], s_c[side][j]);
+        }
     }
-    acc = acc + acc1;
+  }
+  for (int side = 0; side < sides; ++side) {
+    C64 a = acc[side][0] + acc[side][1];
 #pragma unroll
     for (int o = 4; o > 0; o >>= 1) {
-      acc.re += __shfl_xor(acc.re, o, 64);
-      acc.im += __shfl_xor(acc.im, o, 64);
+      a.re += __shfl_xor(a.re, o, 64);
+      a.im += __shfl_xor(a.im, o, 64);
     }
     if (jl == 0) {
       C64 nv = mk(0.0, 0.0);
       if (r < k) {
-        C64* x = side ? q : u;
-        nv = x[r] - acc;
-        x[r] = nv;
+        gp<C64> x = side ? q : u;
+        nv = ldg(x + r) - a;
+        stg(x + r, nv);
       }
       s_u[side][rl] = nv;
     }
   }
   __syncthreads();
   if (!last) {
-    // second-pass partial projections over this block's rows
-    for (int side = 0; side < sides; ++side) {
-      const C64* proj = s.herm ? s.V : (side ? s.V : s.W);
-      C64* out = s.part2 + ((size_t)side * s.nb2 + blockIdx.x) * s.lmax;
-      const int nr = min(SR, k - blockIdx.x * SR);  // rows of this block (s_u is zero past them)
-      for (int j = threadIdx.x; j <= i; j += ST) {
-        const C64* pj = proj + (size_t)j * k + blockIdx.x * SR;
-        C64 t0 = mk(0.0, 0.0), t1 = t0;
-        int w = 0;
-        for (; w + 2 <= nr; w += 2) {
-          t0 = t0 + cmulc(pj[w], s_u[side][w]);
-          t1 = t1 + cmulc(pj[w + 1], s_u[side][w + 1]);
+    // second-pass partial projections over this block's rows: item = (side, j)
+    const int nr = min(SR, k - blockIdx.x * SR);  // rows of this block (s_u is zero past them)
+    for (int it0 = 0; it0 < sides * ncol; it0 += ST / TPJ) {
+      const int item = it0 + (int)threadIdx.x / TPJ;
+      const bool ok = item < sides * ncol;
+      const int side = ok ? item / ncol : 0, j = ok ? item % ncol : 0;
+      gp<const C64> proj = s.herm ? s.V : (side ? s.V : s.W);
+      gp<const C64> pj = proj + (size_t)j * k + blockIdx.x * SR;
+      C64 t0 = mk(0.0, 0.0), t1 = t0;
+      for (int w0 = l4; w0 < nr; w0 += 8 * TPJ) {
+        C64 pv[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int w = w0 + m * TPJ;
+          pv[m] = ldg(pj + (w < nr ? w : 0));
         }
-        if (w < nr) t0 = t0 + cmulc(pj[w], s_u[side][w]);
-        out[j] = t0 + t1;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int w = w0 + m * TPJ;
+          if (w < nr) {
+            if (m & 1)
+              t1 = t1 + cmulc(pv[m], s_u[side][w]);
+            else
+              t0 = t0 + cmulc(pv[m], s_u[side][w]);
+          }
+        }
       }
+      C64 t = t0 + t1;
+#pragma unroll
+      for (int o = 1; o < TPJ; o <<= 1) {
+        t.re += __shfl_xor(t.re, o, 64);
+        t.im += __shfl_xor(t.im, o, 64);
+      }
+      if (ok && l4 == 0) stg(s.part2 + ((size_t)side * s.nb2 + blockIdx.x) * s.lmax + j, t);
     }
     return;
   }
@@ -490,7 +630,7 @@ static int inner_prepare(int k, int hermitian, const C64* alpha, const C64* beta
   NK_HIP(hipMemsetAsync(s.flags, 0, 8 * sizeof(int), st));
   NK_HIP(hipMemsetAsync(s.b, 0, 2 * s.lmax * sizeof(C64), st));
   const size_t lds_lu = k <= TRI_LDS_MAX ? (size_t)3 * k * sizeof(C64) : 0;
-  const size_t lds_inv = k <= TRI_INV_LDS_MAX ? (size_t)k * sizeof(TriF) : 0;
+  const size_t lds_inv = k <= TRI_INV_LDS_MAX ? (size_t)k * (sizeof(TriF) + sizeof(int)) : 0;
   hipLaunchKernelGGL(k_tri_lu, dim3(1), dim3(256), lds_lu, st, k, alpha, beta, delta, tw.Lm, tw.Sw, tw.U0i, tw.U1,
                      tw.U2, s.flags + 1);
   hipLaunchKernelGGL(k_tri_inv, dim3((k + 63) / 64), dim3(64), lds_inv, st, k, tw.Lm, tw.Sw, tw.U0i, tw.U1, tw.U2,
