@@ -95,7 +95,8 @@ __global__ void __launch_bounds__(PTH) k_gj_panel(int ld, const int* __restrict_
         const int r = tid + m * PTH;
         if (r < n) {
           const int pos = s_r2p[r];
-          const double v = cabs1(a[m][t]);
+          double v = cabs1(a[m][t]);
+          if (!(v >= 0.0)) v = 0.0;  // a NaN entry counts as a zero pivot, so some row is always chosen
           if (pos >= c && (v > best || (v == best && pos < bpos))) {
             best = v;
             bpos = pos;
@@ -127,7 +128,7 @@ __global__ void __launch_bounds__(PTH) k_gj_panel(int ld, const int* __restrict_
           bpos = op;
         }
       }
-      const int p = bpos;
+      const int p = bpos < n ? bpos : c;  // (position c is always a candidate)
       const int pr = s_p2r[p];
       const int rc = s_p2r[c];
       if ((pr & (PTH - 1)) == tid) {
@@ -135,9 +136,13 @@ __global__ void __launch_bounds__(PTH) k_gj_panel(int ld, const int* __restrict_
         for (int m = 0; m < RM; ++m) {
           if (m == pr / PTH) {
             const C64 piv = a[m][t];
-            if (!(best > 0.0)) s_sing = 1;
-            const C64 d = cinv(piv);
-            s_ld += log(sqrt(piv.re * piv.re + piv.im * piv.im));
+            // a zero pivot flags the matrix as singular; the elimination
+            // goes on with a zero multiplier instead of 1/0, so no NaN
+            // spreads through the rest of the panel
+            const bool nz = best > 0.0;
+            if (!nz) s_sing = 1;
+            const C64 d = nz ? cinv(piv) : mk(0.0, 0.0);
+            if (nz) s_ld += log(sqrt(piv.re * piv.re + piv.im * piv.im));
 #pragma unroll
             for (int u = 0; u < NB; ++u) s_prow[u] = (u == t) ? d : cmul(a[m][u], d);
           }
@@ -505,6 +510,7 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
   if (tid == 0) {
     iters[b] = it > maxit ? maxit : it;
     if (bad) sing[b] = 1;
+    else if (it > maxit) sing[b] = 2;  // the cap ended the iteration before the stopping test held
   }
 }
 
@@ -628,6 +634,22 @@ static int gj_choose(int batch, int ld, int maxn, const int* nvec, const int* ac
   return NK_OK;
 }
 
+// the warning for a batch: a singular iterate (state 1) or the iteration cap
+// reached before the stopping test held (state 2) in any matrix
+static int rh_outcome(int batch, const int* state, int maxit) {
+  for (int b = 0; b < batch; ++b)
+    if (state[b] == 1) {
+      set_error("Roberts-Higham: singular iterate in matrix %d", b);
+      return NK_WARN_NOTCONV;
+    }
+  for (int b = 0; b < batch; ++b)
+    if (state[b] == 2) {
+      set_error("Roberts-Higham: matrix %d did not converge in %d iterations", b, maxit);
+      return NK_WARN_NOTCONV;
+    }
+  return NK_OK;
+}
+
 int rh_tile_force(int rm, int pth, int tile) {
   std::lock_guard<std::mutex> lock(g_rh_mu);
   if (rm == 0 && pth == 0 && tile == 0) {
@@ -714,12 +736,7 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
       NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
     }
     NK_HIP(hipStreamSynchronize(st));
-    for (int b = 0; b < batch; ++b)
-      if (sing_h[b]) {
-        set_error("Roberts-Higham: singular iterate in matrix %d", b);
-        return NK_WARN_NOTCONV;
-      }
-    return NK_OK;
+    return rh_outcome(batch, sing_h.data(), maxit);
   }
   maxn = 0;
   for (int b = 0; b < batch; ++b) {
@@ -782,11 +799,8 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   }
   NK_HIP(hipStreamSynchronize(st));
   for (int b = 0; b < batch; ++b)
-    if (sing_h[b]) {
-      set_error("Roberts-Higham: singular iterate in matrix %d", b);
-      return NK_WARN_NOTCONV;
-    }
-  return NK_OK;
+    if (act_h[b] && !sing_h[b]) sing_h[b] = 2;  // still active after maxit iterations
+  return rh_outcome(batch, sing_h.data(), maxit);
 }
 
 }  // namespace nk
