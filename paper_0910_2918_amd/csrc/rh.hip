@@ -429,7 +429,9 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
         const unsigned long long ok = __shfl_xor(key, o, 64);
         key = ok > key ? ok : key;
       }
-      const int pr = 0x7fffffff - (int)(key & 0xffffffffu);
+      // every unused row has a nonzero key, and one is unused while t < n; the
+      // fallback only keeps the index in range should that ever not hold
+      const int pr = key ? 0x7fffffff - (int)(key & 0xffffffffu) : t;
       const C64 pv = s_col[par][pr];
       if (!(fabs(pv.re) + fabs(pv.im) > 0.0)) bad = 1;
       const C64 d = cinv(pv);
