@@ -82,6 +82,70 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def stencil_rates(torch, nk, latgen, dev, copy_gbs, reps=100, nsets=10):
+    """The stand-alone stencil at 16^4, mu = 0.3, FP64, on vectors in the
+    library's packed layout (one kernel launch per application): the single
+    operator gamma5 Dw (960 algorithmic B/site: 4 links, one vector in, one
+    out) and the fused pair (A v, A^dag w; 1344 B/site).  'warm' repeats the
+    application on one (gauge, in, out) set, which stays resident in the 256 MB
+    Infinity Cache; 'cold' cycles nsets distinct sets (their gauge fields hold
+    the same values in separate buffers), 629 MB for the single operator and
+    880 MB for the pair, more than twice that cache.  reps back-to-back
+    launches between two HIP events on the launch stream (the ctypes calls are
+    bound beforehand so that the host keeps ahead of the device)."""
+    import ctypes as C
+
+    import numpy as np
+
+    V = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3]
+    u = latgen.random_gauge(DIMS, EPS, 0)
+    src = latgen.random_sources(DIMS, 2, 9)
+    lib = nk.library()
+    sets = []
+    for i in range(nsets):
+        lat = nk.Lattice(DIMS)
+        nk.nk_gauge_set(lat.h, u)
+        canon = [torch.from_numpy(np.ascontiguousarray(src[r]).reshape(-1)).to(dev) for r in range(2)]
+        vp, wp = torch.empty_like(canon[0]), torch.empty_like(canon[0])
+        nk.nk_spinor_pack_device(lat.h, canon[0], vp)
+        nk.nk_spinor_pack_device(lat.h, canon[1], wp)
+        sets.append((lat, vp, wp, torch.empty_like(vp), torch.empty_like(vp)))
+        del canon
+    torch.cuda.synchronize()
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    vptr = lambda t: C.c_void_p(t.data_ptr())
+    single = [(lib.nk_apply_dw_packed_device, (st[0].h, M_W, MU, 1, vptr(st[1]), vptr(st[3]), stream))
+              for st in sets]
+    pair = [(lib.nk_apply_pair_packed_device, (st[0].h, M_W, MU, vptr(st[1]), vptr(st[2]), vptr(st[3]),
+                                               vptr(st[4]), stream)) for st in sets]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def run(calls):
+        for f, a in calls[:4]:  # warm-up
+            if f(*a):
+                raise nk.NKError(-1, nk.nk_last_error())
+        seq = [calls[i % len(calls)] for i in range(reps)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for f, a in seq:
+            f(*a)
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) * 1e3 / reps
+
+    out = {"lattice": "16^4", "mu": MU, "launches": reps, "cold_sets": nsets}
+    for name, calls, bps in (("single", single, 960), ("pair", pair, 1344)):
+        for temp, cl in (("warm", calls[:1]), ("cold", calls)):
+            us = run(cl)
+            gbs = bps * V / us / 1e3
+            out[f"{name}_{temp}"] = {"us": us, "bytes_per_site": bps, "GBps": gbs,
+                                     "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs}
+    for st in sets:
+        st[0].close()
+    del sets, single, pair
+    return out
+
+
 def rel(a, b) -> float:
     import torch
 
@@ -316,6 +380,8 @@ def main() -> int:
         v["k1_frac_of_copy"] = v["k1_GBps"] / copy_gbs
         v["k1_frac_of_peak"] = v["k1_GBps"] / HBM_PEAK_GBS
 
+    stencil = stencil_rates(torch, nk, latgen, dev, copy_gbs)
+
     # the block stencil step: 32 sources in lockstep at 16^3 x 32 (plain,
     # k = 40), per source, beside the one-source kernel on the same lattice
     bdims, nsrc = (16, 16, 16, 32), 32
@@ -429,6 +495,7 @@ def main() -> int:
         "update_kernel": {"avg_launch_us": (t_up / max(n_up, 1)) * 1e3, "launches": int(n_up)},
         "copy_GBps": copy_gbs,
         "step_kernels": step_kernels,
+        "stencil": stencil,
         "block_stencil": block_stencil,
         "learned_scaling_24x24x24x24": rh24,
     }

@@ -163,6 +163,35 @@ int nk_apply_pair_device(nk_lattice* lat, double m_w, double mu,
                          const void* v, const void* w, void* av, void* adw,
                          nk_stream_t stream);
 
+/* The library's own FP64 device layout of a spinor field ("packed"): 12 V
+ * complex128 per vector, component-major, sites in the handle's tile order.
+ * The operator of Sec. 1 is applied there without a layout change, so a caller
+ * that applies it many times (an outer solver) packs once, applies as often as
+ * it needs and unpacks once.  The layout is a permutation of the canonical one,
+ * so sums, norms and inner products are the same in both (up to summation
+ * order); a packed vector is only meaningful on a handle of the same
+ * dimensions.  All four are asynchronous on `stream`; the caller owns every
+ * buffer.  NK_EINVAL on NULL pointers, nrhs < 1 or aliasing input and output;
+ * the two applications return NK_ENOGAUGE before nk_gauge_set. */
+
+/* canonical -> packed for nrhs vectors stored one after another */
+int nk_spinor_pack_device(nk_lattice* lat, const void* x, void* xp, int32_t nrhs, nk_stream_t stream);
+
+/* packed -> canonical for nrhs vectors stored one after another */
+int nk_spinor_unpack_device(nk_lattice* lat, const void* xp, void* x, int32_t nrhs, nk_stream_t stream);
+
+/* yp = [gamma5] Dw(mu) xp on packed vectors: one stencil launch, no scratch
+ * memory.  Bit-identical to nk_apply_dw_device on the same vector. */
+int nk_apply_dw_packed_device(nk_lattice* lat, double m_w, double mu, int32_t gamma5,
+                              const void* xp, void* yp, nk_stream_t stream);
+
+/* The fused pair (avp = A(mu) vp, adwp = A(-mu) wp, A = gamma5 Dw) on packed
+ * vectors: one stencil launch.  Bit-identical to nk_apply_pair_device.
+ * Neither output may alias an input or the other output. */
+int nk_apply_pair_packed_device(nk_lattice* lat, double m_w, double mu,
+                                const void* vp, const void* wp, void* avp, void* adwp,
+                                nk_stream_t stream);
+
 /* The outer Krylov basis only (Sec. 2): k steps of Lanczos (mu == 0) or
  * two-sided Lanczos from x (canonical device vector), in p->precision.
  * Writes the tridiagonal Ritz matrix H_k to host arrays: alpha[2k] (complex

@@ -437,6 +437,46 @@ int nk_apply_pair_device(nk_lattice* lat, double m_w, double mu, const void* v, 
   return NK_OK;
 }
 
+int nk_spinor_pack_device(nk_lattice* lat, const void* x, void* xp, int32_t nrhs, nk_stream_t stream) {
+  if (!lat || !x || !xp || nrhs < 1 || x == xp) {
+    set_error("invalid argument to nk_spinor_pack_device");
+    return NK_EINVAL;
+  }
+  const size_t n = (size_t)12 * lat->g.V;
+  for (int r = 0; r < nrhs; ++r)
+    if (int e = pack_spinor<double>(lat->g, (const C64*)x + r * n, (C64*)xp + r * n, (hipStream_t)stream)) return e;
+  return NK_OK;
+}
+
+int nk_spinor_unpack_device(nk_lattice* lat, const void* xp, void* x, int32_t nrhs, nk_stream_t stream) {
+  if (!lat || !x || !xp || nrhs < 1 || x == xp) {
+    set_error("invalid argument to nk_spinor_unpack_device");
+    return NK_EINVAL;
+  }
+  const size_t n = (size_t)12 * lat->g.V;
+  for (int r = 0; r < nrhs; ++r)
+    if (int e = unpack_spinor<double>(lat->g, (const C64*)xp + r * n, (C64*)x + r * n, (hipStream_t)stream)) return e;
+  return NK_OK;
+}
+
+int nk_apply_dw_packed_device(nk_lattice* lat, double m_w, double mu, int32_t gamma5, const void* xp, void* yp,
+                              nk_stream_t stream) {
+  if (!lat || !xp || !yp || xp == yp) {
+    set_error("invalid argument to nk_apply_dw_packed_device");
+    return NK_EINVAL;
+  }
+  return apply_dw_dev(lat, m_w, mu, gamma5 ? 1 : 0, (const C64*)xp, (C64*)yp, (hipStream_t)stream);
+}
+
+int nk_apply_pair_packed_device(nk_lattice* lat, double m_w, double mu, const void* vp, const void* wp, void* avp,
+                                void* adwp, nk_stream_t stream) {
+  if (!lat || !vp || !wp || !avp || !adwp || avp == adwp || avp == vp || avp == wp || adwp == vp || adwp == wp) {
+    set_error("invalid argument to nk_apply_pair_packed_device");
+    return NK_EINVAL;
+  }
+  return apply_pair_dev(lat, m_w, mu, (const C64*)vp, (const C64*)wp, (C64*)avp, (C64*)adwp, (hipStream_t)stream);
+}
+
 int nk_krylov_basis_device(nk_lattice* lat, const nk_sign_params* p, const void* x, double* alpha, double* beta,
                            double* delta, nk_sign_info* info, nk_stream_t stream) {
   if (int e = validate_params(lat, p)) return e;

@@ -362,6 +362,14 @@ __device__ __forceinline__ unsigned long long piv_key(double v, int r) {
   return ((unsigned long long)__float_as_uint(fv) << 32) | (unsigned)(0x7fffffff - r);
 }
 
+// the small kernel's 32-bit key: the float magnitude with its low eight
+// mantissa bits replaced by 255 - r (r < 128, so never zero), and one
+// unsigned maximum over the wave picks the largest magnitude to 15 mantissa
+// bits, ties to the smaller row
+__device__ __forceinline__ unsigned piv_key32(double v, int r) {
+  return (__float_as_uint((float)v) & ~255u) | (unsigned)(255 - r);
+}
+
 template <int SQ>  // rows per thread; n <= 4 SQ
 __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restrict__ nvec, C64* __restrict__ S_b,
                                                    int scaling, const double* __restrict__ mu_sched, int mu_steps,
@@ -407,7 +415,10 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
       if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
     for (int r = tid; r < n; r += ST_RH) s_used[r] = 0;
-    double logdet = 0.0;
+    // |det| as a running product of |pivot|^2 whose binary exponent is split
+    // off after every step (no logarithm per pivot)
+    double dm = 1.0;
+    int de = 0;
     __syncthreads();
     for (int t = 0; t < n; ++t) {
       const int par = t & 1;
@@ -417,25 +428,25 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
           if (r0 + q < rend) s_col[par][r0 + q] = a[q];
       }
       __syncthreads();
-      unsigned long long key = 0;
+      unsigned key = 0;
       for (int r = lane; r < n; r += 64)
         if (!s_used[r]) {
           const C64 v = s_col[par][r];
-          const unsigned long long kk = piv_key(fabs(v.re) + fabs(v.im), r);
+          const unsigned kk = piv_key32(fabs(v.re) + fabs(v.im), r);
           key = kk > key ? kk : key;
         }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long ok = __shfl_xor(key, o, 64);
-        key = ok > key ? ok : key;
-      }
+      key = __reduce_max_sync(~0ull, key);
       // every unused row has a nonzero key, and one is unused while t < n; the
       // fallback only keeps the index in range should that ever not hold
-      const int pr = key ? 0x7fffffff - (int)(key & 0xffffffffu) : t;
+      const int pr = key ? 255 - (int)(key & 255u) : t;
       const C64 pv = s_col[par][pr];
       if (!(fabs(pv.re) + fabs(pv.im) > 0.0)) bad = 1;
       const C64 d = cinv(pv);
-      if (scaling != NK_RH_NONE) logdet += 0.5 * log(norm2(pv));
+      if (scaling != NK_RH_NONE) {
+        int ex;
+        dm = frexp(dm * norm2(pv), &ex);
+        de += ex;
+      }
       if (colok && pr >= r0 && pr < rend) {
         C64 v = a[0];
 #pragma unroll
@@ -450,20 +461,29 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
         s_pos[pr] = t;
       }
       const C64 rv = s_row[par][c];
-      const bool ct = c == t;
+      // column t keeps nothing of its old value (new entry -f d); every
+      // other column subtracts f times the pivot row: one form for both
+      const double keep = c == t ? 0.0 : 1.0;
       // rows past rend read stale LDS entries; their values are never used
-      // branch-free so that the LDS reads of a chunk are issued together
 #pragma unroll
       for (int q = 0; q < SQ; ++q) {
         const C64 f = s_col[par][min(r0 + q, SMAX - 1)];
-        const C64 base = ct ? mk(0.0, 0.0) : a[q];
-        const C64 upd = base - cmul(f, rv);
-        a[q] = (r0 + q == pr) ? rv : upd;
+        const double tre = fma(-f.im, rv.im, f.re * rv.re);
+        const double tim = fma(f.re, rv.im, f.im * rv.re);
+        a[q] = mk(fma(a[q].re, keep, -tre), fma(a[q].im, keep, -tim));
         if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);  // bound the hoisted LDS reads
+      }
+      // the pivot row takes the scaled row itself (only its segment's threads)
+      if (colok && pr >= r0 && pr < rend) {
+        const int qs = pr - r0;
+#pragma unroll
+        for (int q = 0; q < SQ; ++q)
+          if (q == qs) a[q] = rv;
       }
     }
     __syncthreads();
     // S_{n+1} = (mu S_n + (mu S_n)^{-1}) / 2, inv[pos(r)][rowof(c)] held at (r, c)
+    const double logdet = scaling != NK_RH_NONE ? 0.5 * (log(dm) + de * 0.69314718055994530942) : 0.0;
     double mu = 1.0;
     if (scaling == NK_RH_DET) mu = exp(-logdet / n);
     if (scaling == NK_RH_LEARNED) {  // determinant scaling times the learned correction of this step

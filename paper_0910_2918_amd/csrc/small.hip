@@ -237,7 +237,7 @@ struct Inner {
 struct InnerG {
   int k, herm, lmax, nb1, nb2;
   gp<const C64> B, BH;
-  gp<C64> V, W, uraw[2], qraw[2], part1, part2, a, b, d;
+  gp<C64> V, W, u0, u1, q0, q1, part1, part2, a, b, d;  // u0/u1, q0/q1: the raw ping-pong vectors
   gp<double> part3;
   gp<int> flags;
 };
@@ -253,10 +253,10 @@ __device__ __forceinline__ InnerG inner_view(const Inner& s) {
   g.BH = as_global(s.BH);
   g.V = as_global(s.V);
   g.W = as_global(s.W);
-  for (int h = 0; h < 2; ++h) {
-    g.uraw[h] = as_global(s.uraw[h]);
-    g.qraw[h] = as_global(s.qraw[h]);
-  }
+  g.u0 = as_global(s.uraw[0]);
+  g.u1 = as_global(s.uraw[1]);
+  g.q0 = as_global(s.qraw[0]);
+  g.q1 = as_global(s.qraw[1]);
   g.part1 = as_global(s.part1);
   g.part2 = as_global(s.part2);
   g.part3 = as_global(s.part3);
@@ -265,6 +265,23 @@ __device__ __forceinline__ InnerG inner_view(const Inner& s) {
   g.d = as_global(s.d);
   g.flags = as_global(s.flags);
   return g;
+}
+
+// The descriptor of this block's problem: a kernel argument (read straight
+// from the kernel-argument segment, one round trip less) for a single
+// problem, entry blockIdx.z of a device array for a batch.
+template <bool BATCH>
+__device__ __forceinline__ const Inner& inner_desc(const Inner& s0, const Inner* SS) {
+  if constexpr (BATCH)
+    return SS[blockIdx.z];
+  else
+    return s0;
+}
+
+// raw vector h (0/1) of the u side (q = 0) or the q side (q = 1); selected, not
+// indexed, so that the descriptor stays in registers
+__device__ __forceinline__ gp<C64> rawv(const InnerG& g, int q, int h) {
+  return q ? (h ? g.q1 : g.q0) : (h ? g.u1 : g.u0);
 }
 
 template <int NTH>
@@ -288,24 +305,100 @@ __device__ __forceinline__ void bsum(double (&v)[4]) {
   }
 }
 
+// bsum when only the first wave holds nonzero terms (nb <= 64 partial sums,
+// thread t holding partial t): that wave alone reduces and shares the sums,
+// which equal bsum's (the other waves would add zeros)
+template <int NTH>
+__device__ __forceinline__ void bsum_first(double (&v)[4], int nb) {
+  if (nb > 64) {
+    bsum<NTH>(v);
+    return;
+  }
+  __shared__ double sh1[4];
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sh1[q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = sh1[q];
+}
+
 // Every inner kernel serves a batch of independent problems: problem
 // blockIdx.z is SS[blockIdx.z]; the grid is sized for the largest, and a
 // workgroup beyond its own problem's size or steps returns at once.
-__global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ SS, int i) {
-  const InnerG s = inner_view(SS[blockIdx.z]);
-  if (i >= s.lmax || (int)blockIdx.x >= s.nb1 || s.flags[0]) return;
+// Everything a block loads except the normalisation scale is known at launch
+// (the row of B, the previous raw vector, the old basis entry and the
+// projection columns), so it is all issued before the partial sums of the
+// previous step are reduced: one memory round trip instead of four.  Each
+// wave multiplies its own row's new entry into the projection columns and
+// leaves the products in LDS; they are summed over the block's rows in row
+// order, as a single thread summing them would.
+constexpr int GP = 2;  // projection columns per lane loaded at launch (j < 128)
+
+template <bool BATCH>
+__global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner s0, const Inner* __restrict__ SS, int i) {
+  extern __shared__ C64 s_p[];  // [GR][i + 1] per-row projection products
+  const Inner& S = inner_desc<BATCH>(s0, SS);
+  const InnerG s = inner_view(S);
+  // a batch launch covers the largest problem; a single problem is launched
+  // for exactly its own steps and blocks
+  if (BATCH && (i >= s.lmax || (int)blockIdx.x >= s.nb1)) return;
   const int k = s.k;
   const int side = blockIdx.y;  // 0: u = B v, 1: q = B^dag w
-  gp<const C64> src = side ? s.qraw[i & 1] : s.uraw[i & 1];
-  gp<C64> dst = side ? s.qraw[(i + 1) & 1] : s.uraw[(i + 1) & 1];
-  C64 scal = mk(1.0, 0.0), sub = mk(0.0, 0.0);
-  C64 scal_o = mk(1.0, 0.0);  // scale of the other side's new column
-  if (i > 0) {
-    double v[4] = {0, 0, 0, 0};
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * GR + wave;
+  const bool live = r < k;
+  const int rs = live ? r : 0;  // rows past k load row 0 and discard it
+  // the side-dependent pointers come straight from the descriptor: selected
+  // copies of the local view would keep that view in scratch memory
+  const int h = i & 1;
+  C64* const r0 = side ? S.qraw[0] : S.uraw[0];
+  C64* const r1 = side ? S.qraw[1] : S.uraw[1];
+  gp<const C64> src = as_global((const C64*)(h ? r1 : r0));
+  gp<C64> dst = as_global(h ? r0 : r1);
+  gp<const C64> M = as_global(side ? S.BH : S.B);
+  gp<C64> basis = as_global(side ? S.W : S.V);
+  const bool other = !s.herm;
+  gp<const C64> proj = as_global((const C64*)(s.herm ? S.V : (side ? S.V : S.W)));
+  gp<const C64> osrc = as_global((const C64*)(side ? (h ? S.uraw[1] : S.uraw[0]) : (h ? S.qraw[1] : S.qraw[0])));
+  // loads issued at launch: eight columns of the row and of the raw vector
+  // per lane (clamped to column 0 past the end), this row's raw entries, the
+  // old basis entry and up to GP projection columns per lane
+  C64 mv[8], xv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int c = lane + 64 * u, cc = c < k ? c : 0;
+    mv[u] = ldg(M + (size_t)rs * k + cc);
+    xv[u] = ldg(src + cc);
+  }
+  const C64 xr_raw = ldg(src + rs);
+  const C64 xo_raw = ldg(osrc + rs);
+  const C64 vold = ldg(basis + (size_t)(i > 0 ? i - 1 : 0) * k + rs);
+  C64 pj[GP];
+#pragma unroll
+  for (int m = 0; m < GP; ++m) {
+    const int j = lane + 64 * m;
+    pj[m] = ldg(proj + (size_t)(j < i ? j : 0) * k + rs);
+  }
+  // the previous step's normalisation partial sums (i > 0)
+  double v[4] = {0, 0, 0, 0};
+  if (i > 0)
     for (int bb = threadIdx.x; bb < s.nb2; bb += GR * 64)
 #pragma unroll
       for (int q = 0; q < 4; ++q) v[q] += s.part3[q * s.nb2 + bb];
-    bsum<GR * 64>(v);
+  // a breakdown at an earlier step ends the iteration; the flag is read only
+  // now so that its latency overlaps the loads above (all in bounds)
+  if (s.flags[0]) return;
+  C64 scal = mk(1.0, 0.0), sub = mk(0.0, 0.0);
+  C64 scal_o = mk(1.0, 0.0);  // scale of the other side's new column
+  if (i > 0) {
+    bsum_first<GR * 64>(v, s.nb2);
     const C64 sd = s.herm ? mk(v[2], 0.0) : mk(v[0], v[1]);
     const double sabs = sqrt(norm2(sd));
     if (!(sabs > 1e-14 * sqrt(v[2] * (s.herm ? v[2] : v[3])))) {
@@ -323,71 +416,72 @@ __global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ S
     scal_o = side ? sv : sw;
     sub = side ? mk(delta, 0.0) : beta;
   }
-  __shared__ C64 s_x[GR];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = blockIdx.x * GR + wave;
-  gp<const C64> M = side ? s.BH : s.B;
-  gp<C64> basis = side ? s.W : s.V;
-  if (r < k) {
-    // eight columns per lane and batch, all loads of a batch issued before
-    // the first product (clamped to column 0 past the end)
-    C64 ac[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
-    for (int c0 = lane; c0 < k; c0 += 8 * 64) {
-      C64 mv[8], xv[8];
+  // u_r = (B v_i)_r - sub * v_{i-1, r}: the batch loaded at launch, then
+  // (k > 512) the rest of the row eight columns per lane at a time
+  C64 ac[4] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+  auto madd = [&](int c0) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int c = c0 + 64 * u, cc = c < k ? c : 0;
-        mv[u] = ldg(M + (size_t)r * k + cc);
-        xv[u] = (i > 0) ? ldg(src + cc) : mk(0.0, 0.0);
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int c = c0 + 64 * u;
-        if (c < k) {
-          const C64 x = (i > 0) ? cmul(scal, xv[u]) : mk(c == 0 ? 1.0 : 0.0, 0.0);
-          ac[u & 3] = ac[u & 3] + cmul(mv[u], x);
-        }
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + 64 * u;
+      if (c < k) {
+        const C64 x = (i > 0) ? cmul(scal, xv[u]) : mk(c == 0 ? 1.0 : 0.0, 0.0);
+        ac[u & 3] = ac[u & 3] + cmul(mv[u], x);
       }
     }
-    C64 acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
+  };
+  madd(lane);
+  for (int c0 = lane + 8 * 64; c0 < k; c0 += 8 * 64) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      acc.re += __shfl_xor(acc.re, o, 64);
-      acc.im += __shfl_xor(acc.im, o, 64);
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + 64 * u, cc = c < k ? c : 0;
+      mv[u] = ldg(M + (size_t)rs * k + cc);
+      xv[u] = ldg(src + cc);
     }
-    if (lane == 0) {
-      const C64 xr = (i > 0) ? cmul(scal, ldg(src + r)) : mk(r == 0 ? 1.0 : 0.0, 0.0);
-      stg(basis + (size_t)i * k + r, xr);
-      if (i > 0) acc = acc - cmul(sub, ldg(basis + (size_t)(i - 1) * k + r));
-      stg(dst + r, acc);
-      s_x[wave] = acc;
+    madd(c0);
+  }
+  C64 acc = (ac[0] + ac[1]) + (ac[2] + ac[3]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.re += __shfl_xor(acc.re, o, 64);
+    acc.im += __shfl_xor(acc.im, o, 64);
+  }
+  const C64 xr = (i > 0) ? cmul(scal, xr_raw) : mk(r == 0 ? 1.0 : 0.0, 0.0);  // v_i (or w_i) at row r
+  if (i > 0) acc = acc - cmul(sub, vold);
+  if (live && lane == 0) {
+    stg(basis + (size_t)i * k + r, xr);
+    stg(dst + r, acc);
+  }
+  // this row's terms of the first-pass projections W^dag u (V^dag q): column
+  // i of the other basis is being written by the other side's blocks in this
+  // launch, so its entry is formed here from the raw vector (Hermitian: it
+  // is this row's own new entry)
+  const int ncol = i + 1;
+  for (int m0 = 0; m0 * 64 < ncol; m0 += GP) {
+#pragma unroll
+    for (int m = 0; m < GP; ++m) {
+      const int j = lane + 64 * (m0 + m);
+      if (j < ncol) {
+        C64 pv;
+        if (j == i) pv = other ? ((i > 0) ? cmul(scal_o, xo_raw) : mk(r == 0 ? 1.0 : 0.0, 0.0)) : xr;
+        else pv = (m0 == 0) ? pj[m] : ldg(proj + (size_t)j * k + rs);
+        s_p[wave * ncol + j] = cmulc(pv, acc);
+      }
     }
-  } else if (lane == 0) {
-    s_x[wave] = mk(0.0, 0.0);
   }
   __syncthreads();
-  // partial first-pass projections over this block's rows.  Column i of the
-  // other basis is being written by the other side's blocks in this same
-  // launch, so its entries are recomputed here from the raw vector.
-  const bool other = !s.herm;
-  gp<const C64> proj = s.herm ? s.V : (side ? s.V : s.W);
-  gp<const C64> osrc = side ? s.uraw[i & 1] : s.qraw[i & 1];
   gp<C64> out = s.part1 + ((size_t)side * s.nb1 + blockIdx.x) * s.lmax;
-  for (int j = threadIdx.x; j <= i; j += GR * 64) {
+  for (int j = threadIdx.x; j < ncol; j += GR * 64) {
     C64 t = mk(0.0, 0.0);
 #pragma unroll
-    for (int w = 0; w < GR; ++w) {
-      const int rr = blockIdx.x * GR + w;
-      if (rr < k) {
-        C64 pv;
-        if (j == i && other) pv = (i > 0) ? cmul(scal_o, ldg(osrc + rr)) : mk(rr == 0 ? 1.0 : 0.0, 0.0);
-        else pv = ldg(proj + (size_t)j * k + rr);
-        t = t + cmulc(pv, s_x[w]);
-      }
-    }
+    for (int w = 0; w < GR; ++w)
+      if (blockIdx.x * GR + w < k) t = t + s_p[w * ncol + j];
     stg(out + j, t);
   }
 }
+
+// dynamic LDS of k_in_gemv at step i: GR x (i + 1) products (128 KB at the
+// largest inner size)
+static size_t gemv_lds(int i) { return (size_t)GR * (i + 1) * sizeof(C64); }
 
 // pass 1 (last == 0): reduce part1, subtract, emit part2;
 // pass 2 (last == 1): reduce part2, subtract, emit the normalisation sums.
@@ -397,9 +491,10 @@ __global__ void __launch_bounds__(GR * 64) k_in_gemv(const Inner* __restrict__ S
 // in the same batch.
 constexpr int TPJ = 4;  // lanes per (side, column) in the reduction phases
 
-__global__ void __launch_bounds__(ST) k_in_sub(const Inner* __restrict__ SS, int i, int last) {
-  const InnerG s = inner_view(SS[blockIdx.z]);
-  if (i >= s.lmax || (last && i + 1 >= s.lmax) || (int)blockIdx.x >= s.nb2 || s.flags[0]) return;
+template <bool BATCH>
+__global__ void __launch_bounds__(ST) k_in_sub(const Inner s0, const Inner* __restrict__ SS, int i, int last) {
+  const InnerG s = inner_view(inner_desc<BATCH>(s0, SS));
+  if (BATCH && (i >= s.lmax || (last && i + 1 >= s.lmax) || (int)blockIdx.x >= s.nb2)) return;
   const int k = s.k;
   const int sides = s.herm ? 1 : 2;
   __shared__ C64 s_c[2][LMAX];
@@ -437,18 +532,20 @@ __global__ void __launch_bounds__(ST) k_in_sub(const Inner* __restrict__ SS, int
       t.re += __shfl_xor(t.re, o, 64);
       t.im += __shfl_xor(t.im, o, 64);
     }
-    if (ok && l4 == 0) {
-      s_c[side][j] = t;
-      if (!last && side == 0 && j == i && blockIdx.x == 0) stg(s.a + i, s.herm ? mk(t.re, 0.0) : t);
-    }
+    if (ok && l4 == 0) s_c[side][j] = t;
   }
+  // a breakdown flagged at this or an earlier step ends the iteration; the
+  // flag is read only now so that its latency overlaps the loads above (all
+  // in bounds)
+  if (s.flags[0]) return;
   __syncthreads();
+  if (!last && blockIdx.x == 0 && threadIdx.x == 0) stg(s.a + i, s.herm ? mk(s_c[0][i].re, 0.0) : s_c[0][i]);
   // u -= V c, q -= W d: eight lanes per row, columns jl, jl + 8, ... of both
   // sides in one batch of loads
   const int rl = threadIdx.x >> 3, jl = threadIdx.x & 7;
   const int r = blockIdx.x * SR + rl;
-  gp<C64> u = s.uraw[(i + 1) & 1];
-  gp<C64> q = s.qraw[(i + 1) & 1];
+  gp<C64> u = rawv(s, 0, (i + 1) & 1);
+  gp<C64> q = rawv(s, 1, (i + 1) & 1);
   C64 acc[2][2] = {{mk(0.0, 0.0), mk(0.0, 0.0)}, {mk(0.0, 0.0), mk(0.0, 0.0)}};
   if (r < k) {
     for (int j0 = jl; j0 <= i; j0 += 8 * 8) {
@@ -683,9 +780,9 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
   if (int e = inner_prepare(k, hermitian, alpha, beta, delta, s, tw, st)) return e;
   const int sides = hermitian ? 1 : 2;
   for (int i = 0; i < ell; ++i) {
-    hipLaunchKernelGGL(k_in_gemv, dim3(s.nb1, sides, 1), dim3(GR * 64), 0, st, sdev, i);
-    hipLaunchKernelGGL(k_in_sub, dim3(s.nb2, 1, 1), dim3(ST), 0, st, sdev, i, 0);
-    if (i + 1 < ell) hipLaunchKernelGGL(k_in_sub, dim3(s.nb2, 1, 1), dim3(ST), 0, st, sdev, i, 1);
+    hipLaunchKernelGGL(k_in_gemv<false>, dim3(s.nb1, sides, 1), dim3(GR * 64), gemv_lds(i), st, s, nullptr, i);
+    hipLaunchKernelGGL(k_in_sub<false>, dim3(s.nb2, 1, 1), dim3(ST), 0, st, s, nullptr, i, 0);
+    if (i + 1 < ell) hipLaunchKernelGGL(k_in_sub<false>, dim3(s.nb2, 1, 1), dim3(ST), 0, st, s, nullptr, i, 1);
   }
   NK_HIP(hipGetLastError());
   int* iflags = s.flags;
@@ -758,9 +855,9 @@ int small_inner_batch(int r, const int* k, const int* ell, int hermitian, const 
   NK_HIP(hipMemcpyAsync(sdev, S.data(), r * sizeof(Inner), hipMemcpyHostToDevice, st));
   const int sides = hermitian ? 1 : 2;
   for (int i = 0; i < lmax; ++i) {
-    hipLaunchKernelGGL(k_in_gemv, dim3(nb1, sides, r), dim3(GR * 64), 0, st, sdev, i);
-    hipLaunchKernelGGL(k_in_sub, dim3(nb2, 1, r), dim3(ST), 0, st, sdev, i, 0);
-    if (i + 1 < lmax) hipLaunchKernelGGL(k_in_sub, dim3(nb2, 1, r), dim3(ST), 0, st, sdev, i, 1);
+    hipLaunchKernelGGL(k_in_gemv<true>, dim3(nb1, sides, r), dim3(GR * 64), gemv_lds(i), st, Inner{}, sdev, i);
+    hipLaunchKernelGGL(k_in_sub<true>, dim3(nb2, 1, r), dim3(ST), 0, st, Inner{}, sdev, i, 0);
+    if (i + 1 < lmax) hipLaunchKernelGGL(k_in_sub<true>, dim3(nb2, 1, r), dim3(ST), 0, st, Inner{}, sdev, i, 1);
   }
   NK_HIP(hipGetLastError());
   std::vector<int> fl((size_t)2 * r);

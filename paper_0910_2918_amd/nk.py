@@ -52,6 +52,10 @@ EXPORTS = (
     "nk_apply_dw",
     "nk_apply_dw_device",
     "nk_apply_pair_device",
+    "nk_spinor_pack_device",
+    "nk_spinor_unpack_device",
+    "nk_apply_dw_packed_device",
+    "nk_apply_pair_packed_device",
     "nk_krylov_basis_device",
     "nk_small_sign",
     "nk_rh_sign",
@@ -152,6 +156,10 @@ def library():
         "nk_apply_dw": (C.c_int, [vp, dbl, dbl, i32, vp, vp, i32]),
         "nk_apply_dw_device": (C.c_int, [vp, dbl, dbl, i32, vp, vp, i32, vp]),
         "nk_apply_pair_device": (C.c_int, [vp, dbl, dbl, vp, vp, vp, vp, vp]),
+        "nk_spinor_pack_device": (C.c_int, [vp, vp, vp, i32, vp]),
+        "nk_spinor_unpack_device": (C.c_int, [vp, vp, vp, i32, vp]),
+        "nk_apply_dw_packed_device": (C.c_int, [vp, dbl, dbl, i32, vp, vp, vp]),
+        "nk_apply_pair_packed_device": (C.c_int, [vp, dbl, dbl, vp, vp, vp, vp, vp]),
         "nk_krylov_basis_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, vp, vp, P(nk_sign_info), vp]),
         "nk_small_sign": (C.c_int, [i32, i32, i32, vp, vp, vp, P(nk_sign_params), vp, P(nk_sign_info)]),
         "nk_rh_sign": (C.c_int, [i32, i32, P(i32), vp, i32, i32, dbl, P(i32)]),
@@ -278,6 +286,24 @@ def nk_apply_dw_device(h, m_w: float, mu: float, gamma5: bool, x, y, nrhs: int =
 
 def nk_apply_pair_device(h, m_w: float, mu: float, v, w, av, adw, stream=None) -> None:
     _check(library().nk_apply_pair_device(h, m_w, mu, _dptr(v), _dptr(w), _dptr(av), _dptr(adw), _stream(stream)))
+
+
+def nk_spinor_pack_device(h, x, xp, nrhs: int = 1, stream=None) -> None:
+    """canonical -> the library's packed FP64 device layout"""
+    _check(library().nk_spinor_pack_device(h, _dptr(x), _dptr(xp), nrhs, _stream(stream)))
+
+
+def nk_spinor_unpack_device(h, xp, x, nrhs: int = 1, stream=None) -> None:
+    _check(library().nk_spinor_unpack_device(h, _dptr(xp), _dptr(x), nrhs, _stream(stream)))
+
+
+def nk_apply_dw_packed_device(h, m_w: float, mu: float, gamma5: bool, xp, yp, stream=None) -> None:
+    _check(library().nk_apply_dw_packed_device(h, m_w, mu, 1 if gamma5 else 0, _dptr(xp), _dptr(yp), _stream(stream)))
+
+
+def nk_apply_pair_packed_device(h, m_w: float, mu: float, vp, wp, avp, adwp, stream=None) -> None:
+    _check(library().nk_apply_pair_packed_device(h, m_w, mu, _dptr(vp), _dptr(wp), _dptr(avp), _dptr(adwp),
+                                                 _stream(stream)))
 
 
 def nk_krylov_basis_device(h, params: nk_sign_params, x, stream=None):
