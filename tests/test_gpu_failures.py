@@ -8,6 +8,10 @@ made to fault).
 * the iteration cap reached before the stopping test -> NK_WARN_NOTCONV;
 * a source with a NaN -> NK_EINVAL;
 * V_k larger than the device with two-pass lifting switched off -> NK_ENOMEM;
+* a serious breakdown of two-sided Lanczos at its first step (a free-field
+  plane wave times a spinor with w_hat^dag v_hat = 0) -> NK_WARN_BREAKDOWN and
+  the result of the steps before it, alone and next to an ordinary source in
+  a lockstep run;
 * and the exact case at the other end: a source that is an eigenvector of
   gamma5 Dw(mu) (a free-field plane wave) comes back as sgn(Re lambda) x.
 """
@@ -16,6 +20,10 @@ import pytest
 
 import latgen
 from oracle import freefield as F
+from oracle import krylov as K
+from oracle import nested as N
+from oracle import wilson as W
+from tests import breakdown_source as BS
 from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
@@ -132,4 +140,62 @@ def test_eigenvector_source_gives_sign_of_its_eigenvalue(mu, ell):
         b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=30, ell=ell, mu=mu), dx, dy)
         y = to_host(dy)
         assert rel(y, np.sign(lam.real) * psi.reshape(-1)) < 1e-10, (n, lam)
+    lat.close()
+
+
+def _breakdown_case(mu):
+    """(x, y_ref): the breakdown source and the oracle's result from its one
+    basis vector, sgn(Re alpha_0) x."""
+    s, r = BS.breakdown_spinor(M_W, mu)
+    assert r < 1e-14
+    x = BS.plane_wave(s)
+    u = latgen.unit_gauge(BS.DIMS)
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    kr = K.two_sided_lanczos(f, fd, x.reshape(-1), 20)
+    assert kr.breakdown == 1 and kr.H.k == 1
+    z, _ = N.small_sign(kr.H, 0, False)
+    y = kr.norm_x * kr.V @ z
+    assert rel(y, np.sign(kr.H.alpha[0].real) * x.reshape(-1)) < 1e-13
+    return x, y
+
+
+@pytest.mark.parametrize("mu", [0.3, 0.5])
+@pytest.mark.parametrize("ell", [0, 4])
+def test_two_sided_serious_breakdown(mu, ell):
+    b = nk()
+    x, yref = _breakdown_case(mu)
+    lat, _ = make_lattice(BS.DIMS, 0.0, unit=True)
+    banner(f"2sL serious breakdown at step 1, mu={mu} ell={ell}")
+    dx = to_dev(x)
+    dy = torch_cuda().empty_like(dx)
+    info, rc = b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=20, ell=ell, mu=mu), dx, dy)
+    assert rc == b.NK_WARN_BREAKDOWN
+    assert info.breakdown_step == 1 and info.k_used == 1
+    assert rel(to_host(dy), yref) < 1e-12
+    lat.close()
+
+
+def test_lockstep_breakdown_leaves_the_other_source_alone():
+    """block = 1 with the breakdown source beside a Gaussian one: the first
+    stops after one step, the second runs all k steps and agrees with its
+    own single-source run."""
+    b = nk()
+    mu, k, ell = 0.3, 24, 6
+    x0, y0ref = _breakdown_case(mu)
+    x1 = latgen.random_sources(BS.DIMS, 1, 11)[0]
+    lat, _ = make_lattice(BS.DIMS, 0.0, unit=True)
+    torch = torch_cuda()
+    banner("lockstep: breakdown source next to a Gaussian source")
+    d1 = to_dev(x1)
+    y1 = torch.empty_like(d1)
+    _, rc1 = b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=k, ell=ell, mu=mu), d1, y1)
+    assert rc1 == b.NK_OK
+    xb = to_dev(np.stack([x0, x1]))
+    yb = torch.empty_like(xb)
+    info, rc = b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=k, ell=ell, mu=mu, nrhs=2, block=1), xb, yb)
+    assert rc == b.NK_WARN_BREAKDOWN and info.breakdown_step == 1
+    ybh = to_host(yb).reshape(2, -1)
+    assert rel(ybh[0], y0ref) < 1e-12
+    assert rel(ybh[1], to_host(y1)) < 1e-9
     lat.close()

@@ -87,3 +87,27 @@ def test_dense_tridiagonal_layout():
     h = t.dense()
     assert h[0, 1] == 4.0 and h[1, 0] == 6.0 and h[2, 1] == 7.0 and h[1, 2] == 5.0
     assert np.count_nonzero(h) == 7
+
+
+@pytest.mark.parametrize("mu", [0.3, 0.5])
+def test_serious_breakdown_on_a_free_field_plane_wave(mu):
+    """The lattice operator itself: a plane wave times a spinor with
+    w_hat^dag v_hat = 0 (tests/breakdown_source.py) stops the oracle's 2sL
+    after one step, while v_hat and w_hat are far from zero."""
+    from tests import breakdown_source as B
+
+    s, r = B.breakdown_spinor(M_W, mu)
+    assert r < 1e-14
+    M = B.momentum_matrix(M_W, mu)
+    a = s.conj() @ M @ s
+    assert np.linalg.norm(M @ s - a * s) > 0.1  # not an eigenvector
+    x = B.plane_wave(s)
+    u = latgen.unit_gauge(B.DIMS)
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    # the plane wave stays in its four spinor directions at p
+    assert np.linalg.norm(f(x.reshape(-1)) - B.plane_wave(M @ s).reshape(-1)) < 1e-13
+    kr = K.two_sided_lanczos(f, fd, x.reshape(-1), 10)
+    assert kr.breakdown == 1
+    assert kr.H.k == 1
+    assert abs(kr.H.alpha[0] - a) < 1e-13
