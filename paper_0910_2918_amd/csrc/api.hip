@@ -288,6 +288,8 @@ nk_lattice::~nk_lattice() {
   canon.release();
   lift.release();
   tmp.release();
+  bvec.release();
+  bsmall.release();
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
 }
 
@@ -525,7 +527,7 @@ int nk_small_sign(int32_t k, int32_t ell, int32_t hermitian, const double* alpha
   nk_sign_params dp;
   nk_sign_params_default(&dp);
   if (!p) p = &dp;
-  DevBuf buf;
+  ScopedBuf buf;
   if (buf.ensure((size_t)4 * k * sizeof(C64))) return NK_ENOMEM;
   C64* a = buf.as<C64>();
   NK_HIP(hipMemcpy(a, alpha, k * sizeof(C64), hipMemcpyHostToDevice));
@@ -553,7 +555,7 @@ int nk_inner_matrix(int32_t k, int32_t ell, int32_t hermitian, const double* alp
     set_error("invalid argument to nk_inner_matrix");
     return NK_EINVAL;
   }
-  DevBuf buf;
+  ScopedBuf buf;
   if (buf.ensure((size_t)4 * k * sizeof(C64))) return NK_ENOMEM;
   C64* c = buf.as<C64>();
   NK_HIP(hipMemcpy(c, alpha, k * sizeof(C64), hipMemcpyHostToDevice));
@@ -615,7 +617,7 @@ int nk_rh_features_device(int32_t batch, int32_t ld, const int32_t* n, const voi
       set_error("matrix %d has size %d outside [1, ld=%d]", b, n[b], ld);
       return NK_EINVAL;
     }
-  DevBuf nb;
+  ScopedBuf nb;
   if (nb.ensure((size_t)batch * sizeof(int))) return NK_ENOMEM;
   NK_HIP(hipMemcpyAsync(nb.p, n, batch * sizeof(int), hipMemcpyHostToDevice, stream));
   if (int e = mlp_features(batch, ld, nb.as<int>(), (const C64*)S, feat, stream)) return e;
@@ -671,7 +673,7 @@ int nk_rh_sign(int32_t batch, int32_t ld, const int32_t* n, double* S, int32_t s
       set_error("matrix %d has size %d outside [0, ld=%d]", b, n[b], ld);
       return NK_EINVAL;
     }
-  DevBuf buf;
+  ScopedBuf buf;
   const size_t bytes = (size_t)batch * ld * ld * sizeof(C64);
   if (buf.ensure(bytes)) return NK_ENOMEM;
   NK_HIP(hipMemcpy(buf.p, S, bytes, hipMemcpyHostToDevice));
@@ -721,7 +723,7 @@ int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, dou
     return NK_EINVAL;
   }
   const size_t n = (size_t)12 * lat->g.V * p->nrhs;
-  DevBuf io;
+  ScopedBuf io;
   if (io.ensure(2 * n * sizeof(C64))) return NK_ENOMEM;
   C64* dx = io.as<C64>();
   C64* dy = dx + n;

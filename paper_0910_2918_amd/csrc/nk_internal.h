@@ -173,6 +173,17 @@ struct DevBuf {
   T* as() const { return reinterpret_cast<T*>(p); }
 };
 
+// A function-local workspace, released when it goes out of scope (hipFree
+// waits for the device, so no kernel still reads it).  File-scope buffers and
+// the handle's buffers are plain DevBufs: the handle releases its own in its
+// destructor, and file-scope ones live until the process ends.
+struct ScopedBuf : DevBuf {
+  ScopedBuf() = default;
+  ScopedBuf(const ScopedBuf&) = delete;
+  ScopedBuf& operator=(const ScopedBuf&) = delete;
+  ~ScopedBuf() { release(); }
+};
+
 }  // namespace nk
 
 // the opaque handle

@@ -278,10 +278,19 @@ __device__ __forceinline__ const Inner& inner_desc(const Inner& s0, const Inner*
     return s0;
 }
 
-// raw vector h (0/1) of the u side (q = 0) or the q side (q = 1); selected, not
-// indexed, so that the descriptor stays in registers
+// c ? a : b for two fields of a local descriptor.  A plain select of two
+// fields lets the compiler turn it into one load through a selected address,
+// which keeps the whole descriptor in scratch memory; passing both values
+// through an empty asm first leaves a select of registers.
+template <class T>
+__device__ __forceinline__ T pick(bool c, T a, T b) {
+  asm volatile("" : "+s"(a), "+s"(b));
+  return c ? a : b;
+}
+
+// raw vector h (0/1) of the u side (q = 0) or the q side (q = 1)
 __device__ __forceinline__ gp<C64> rawv(const InnerG& g, int q, int h) {
-  return q ? (h ? g.q1 : g.q0) : (h ? g.u1 : g.u0);
+  return pick(q != 0, pick(h != 0, g.q1, g.q0), pick(h != 0, g.u1, g.u0));
 }
 
 template <int NTH>
@@ -499,8 +508,8 @@ __global__ void __launch_bounds__(ST) k_in_sub(const Inner s0, const Inner* __re
   const int sides = s.herm ? 1 : 2;
   __shared__ C64 s_c[2][LMAX];
   __shared__ C64 s_u[2][SR];
-  gp<const C64> pin = last ? s.part2 : s.part1;
-  const int nbin = last ? s.nb2 : s.nb1;
+  gp<const C64> pin = pick(last != 0, s.part2, s.part1);
+  const int nbin = pick(last != 0, s.nb2, s.nb1);
   const int ncol = i + 1;
   const int l4 = threadIdx.x & (TPJ - 1);
   // reduce the partial projections: item = (side, j), TPJ lanes each
@@ -593,7 +602,7 @@ __global__ void __launch_bounds__(ST) k_in_sub(const Inner s0, const Inner* __re
       const int item = it0 + (int)threadIdx.x / TPJ;
       const bool ok = item < sides * ncol;
       const int side = ok ? item / ncol : 0, j = ok ? item % ncol : 0;
-      gp<const C64> proj = s.herm ? s.V : (side ? s.V : s.W);
+      gp<const C64> proj = pick(s.herm || side, s.V, s.W);
       gp<const C64> pj = proj + (size_t)j * k + blockIdx.x * SR;
       C64 t0 = mk(0.0, 0.0), t1 = t0;
       for (int w0 = l4; w0 < nr; w0 += 8 * TPJ) {

@@ -199,3 +199,38 @@ def test_lockstep_breakdown_leaves_the_other_source_alone():
     assert rel(ybh[0], y0ref) < 1e-12
     assert rel(ybh[1], to_host(y1)) < 1e-9
     lat.close()
+
+
+def test_destroyed_handles_and_host_calls_free_their_device_memory():
+    """A cycle of handle create, host-pointer application, lockstep run and
+    destroy, twice: the second cycle ends with as much free device memory as
+    the first (the library's file-scope workspaces are sized by the first)."""
+    b = nk()
+    torch = torch_cuda()
+    dims = (8, 8, 8, 8)
+    u = latgen.random_gauge(dims, 0.6, 2)
+    xs = latgen.random_sources(dims, 2, 3)
+
+    def cycle():
+        lat = b.Lattice(dims)
+        b.nk_gauge_set(lat.h, u)
+        y = np.empty_like(xs[0].reshape(-1))
+        info = b.nk_sign_info()
+        p = b.nk_sign_params_default(k=60, ell=20, mu=0.3)
+        rc = b.library().nk_sign_apply(lat.h, b.C.byref(p), b._hptr(np.ascontiguousarray(xs[0].reshape(-1))),
+                                       b._hptr(y), b.C.byref(info))
+        assert rc == b.NK_OK
+        dx = to_dev(xs)
+        dy = torch.empty_like(dx)
+        _, rc = b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=60, ell=20, mu=0.3, nrhs=2, block=1), dx, dy)
+        assert rc == b.NK_OK
+        del dx, dy
+        lat.close()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return torch.cuda.mem_get_info()[0]
+
+    banner("handle create/apply/destroy twice: no device memory kept")
+    f1 = cycle()
+    f2 = cycle()
+    assert f2 >= f1 - (16 << 20), (f1, f2)

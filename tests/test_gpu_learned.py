@@ -255,3 +255,44 @@ def rh_train_params():
         return np.load(rh_train.WEIGHTS).astype(np.float32)
     p = latgen.mlp_init(0)
     return p
+
+
+def test_full_size_learned_configuration():
+    """The learned-scaling workload at its full size: 24^4, mu = 0.5, link
+    width 1.0, k = 1200, l = 250, with the shipped weights.  Properties that
+    hold at any size: the learned and the unscaled iterations give the same
+    vector (sgn(mu S) = sgn(S)) and the learned one takes no more
+    Roberts-Higham iterations; sgn(sgn x) = x; and the two-pass lift
+    reproduces the one-pass vector."""
+    torch = torch_cuda()
+    b = nk()
+    from .gpu_helpers import make_lattice, rel, to_dev
+
+    dims, k, ell, mu = (24, 24, 24, 24), 1200, 250, 0.5
+    torch.cuda.empty_cache()  # the one-pass lift stores V_k: 76.5 GB
+    lat, _ = make_lattice(dims, 1.0, 0)
+    x = to_dev(latgen.random_sources(dims, 1, 5)[0])
+    y0, y1, y2, yy = (torch.empty_like(x) for _ in range(4))
+    banner(f"24^4 mu={mu} k={k} l={ell}: learned vs unscaled, sgn(sgn x) = x, two-pass")
+    b.nk_rh_model_set(rh_train_params())
+    try:
+        pl = b.nk_sign_params_default(k=k, ell=ell, mu=mu, rh_scaling=b.NK_RH_LEARNED, two_pass=b.NK_TWO_PASS_OFF)
+        i1, rc1 = b.nk_sign_apply_device(lat.h, pl, x, y1)
+        _, rcs = b.nk_sign_apply_device(lat.h, pl, y1, yy)
+        pt = b.nk_sign_params_default(k=k, ell=ell, mu=mu, rh_scaling=b.NK_RH_LEARNED, two_pass=b.NK_TWO_PASS_ON)
+        i2, rc2 = b.nk_sign_apply_device(lat.h, pt, x, y2)
+    finally:
+        b.nk_rh_model_set(None)
+    i0, rc0 = b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=k, ell=ell, mu=mu), x, y0)
+    assert rc0 == rc1 == rc2 == rcs == b.NK_OK
+    r_same = rel(y1.cpu().numpy(), y0.cpu().numpy())
+    r_sq = rel(yy.cpu().numpy(), x.cpu().numpy())
+    r_tp = rel(y2.cpu().numpy(), y1.cpu().numpy())
+    print(f"rh iterations unscaled {i0.rh_iters}, learned {i1.rh_iters}; learned vs unscaled {r_same:.2e}; "
+          f"sgn^2 residual {r_sq:.2e}; two-pass vs one-pass {r_tp:.2e}", flush=True)
+    assert i2.two_pass == 1 and i1.two_pass == 0
+    assert i1.rh_iters <= i0.rh_iters
+    assert r_same < 1e-10
+    assert r_sq < 1e-6
+    assert r_tp < 1e-14
+    lat.close()
