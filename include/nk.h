@@ -23,8 +23,16 @@
  *
  * Ownership: callers own every buffer they pass.  The library copies what it
  * needs and keeps no user pointer after a call returns.  It owns its device
- * workspaces (Krylov bases etc.), sized on first use and freed by
- * nk_lattice_destroy.  A handle is not thread-safe: serialise calls on it.
+ * workspaces: a handle's (Krylov bases etc.) are sized on first use and freed
+ * by nk_lattice_destroy; the process-wide ones of the small problem, the
+ * Roberts-Higham iteration and the learned model grow to the largest problem
+ * seen and are kept until the process ends.
+ *
+ * Threads: calls on one handle must be serialised.  So must, across all
+ * handles, every call that reaches the process-wide workspaces:
+ * nk_sign_apply[_device], nk_small_sign, nk_inner_matrix, nk_rh_sign,
+ * nk_rh_model_set and the learned-scaling kernels.  nk_rh_tile_force and
+ * nk_rh_tile_choice are thread-safe.
  *
  * Errors: every entry point returns 0 (NK_OK) on success, a negative code on
  * failure (outputs unspecified) or a positive warning (outputs valid).
