@@ -26,6 +26,7 @@ subspace method for the overlap operator", PoS LATTICE2009):
 Pins: every function is checked by ``tests/test_oracle_*.py`` against
 something other than itself (closed forms, library routines taking a
 different route, algebraic identities, brute force on tiny lattices).
-Parity unpinned: ``nested.convergence_estimate`` (the paper defines no
-estimator; only sanity bounds are tested).
+``nested.convergence_estimate`` (the paper defines no estimator) is pinned at
+mu = 0, where the outer basis is orthonormal, between the true errors against
+the exact sign; on the two-sided coefficients (mu != 0) it is a heuristic.
 """

@@ -88,7 +88,9 @@ def convergence_estimate(H: Tridiag, ell: int, hermitian: bool, d: int, **rhkw) 
     """Relative change of the small-problem vector between k - d and k outer steps.
 
     est = ||z^{(k)} - [z^{(k-d)}; 0]|| / ||z^{(k)}||.  The paper defines no
-    estimator; this one is a heuristic (parity unpinned).
+    estimator.  With an orthonormal outer basis (Lanczos, mu = 0) it equals
+    ||y_k - y_{k-d}|| / ||y_k|| and is pinned between the true errors against
+    the exact sign; on the two-sided coefficients (mu != 0) it is a heuristic.
     """
     k = H.k
     z1, _ = small_sign(H, ell, hermitian, **rhkw)

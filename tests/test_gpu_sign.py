@@ -167,6 +167,24 @@ def test_early_stop(cfg1):
     assert rel(y, ref) < 1e-6
 
 
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+@pytest.mark.parametrize("ell", [0, 20])
+def test_convergence_estimate_matches_oracle(cfg1, mu, ell):
+    """info.est at (k, d) without early stopping against the oracle's estimate
+    on its own H_k of the same recurrence (R15; the estimate itself is pinned
+    against the exact sign in the oracle tests at mu = 0)."""
+    lat, u, x = cfg1
+    k, d = 60, 10
+    banner(f"4^4 estimate k={k} d={d} ell={ell} mu={mu}")
+    _, info, rc = _sign(lat, x, k=k, ell=ell, mu=mu, est_delay=d)
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    kr = N.outer_basis(f, fd, x.reshape(-1), k, mu == 0.0)
+    ref = N.convergence_estimate(kr.H, ell, mu == 0.0, d)
+    assert rc == 0 and 1e-6 < ref < 1.0
+    assert abs(info.est - ref) < 1e-6 * ref
+
+
 def test_ginsparg_wilson_on_gpu(cfg1):
     lat, u, x = cfg1
     banner("4^4 Ginsparg-Wilson relation of Dov")

@@ -142,3 +142,30 @@ def test_convergence_estimate_sanity(basis):
     herm = mu == 0.0
     est = N.convergence_estimate(kr.H, 0, herm, 10)
     assert 0.0 < est < 1.0
+
+
+@pytest.mark.parametrize("k,d,ell", [(40, 10, 0), (60, 5, 0), (60, 10, 20), (90, 20, 30), (120, 10, 40)])
+def test_convergence_estimate_between_the_true_errors(k, d, ell):
+    """The estimate (R15) pinned against the exact sign.  At mu = 0 with a
+    fully reorthogonalised Lanczos basis V_k has orthonormal columns, so
+    est ||y_k|| = ||y_k - y_{k-d}|| with y_j = ||x|| V_j z^{(j)}; the triangle
+    inequality against the exact spectral sign y* (stored 4^4 result) then
+    brackets it: |e_{k-d} - e_k| <= est ||y_k|| <= e_{k-d} + e_k, with
+    e_j = ||y_j - y*||."""
+    import os
+
+    dims = (4, 4, 4, 4)
+    u = latgen.random_gauge(dims, 0.4, 0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sign_4x4x4x4_mu0_eps0.4.npy"))
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, 0.0).reshape(-1)
+    kr = K.lanczos(f, x.reshape(-1), k, reorth=True)
+    assert np.linalg.norm(kr.V.conj().T @ kr.V - np.eye(kr.V.shape[1])) < 1e-13
+    est = N.convergence_estimate(kr.H, ell, True, d)
+    z1, _ = N.small_sign(kr.H, ell, True)
+    z0, _ = N.small_sign(kr.H.leading(k - d), min(ell, k - d) if ell else 0, True)
+    y1 = kr.norm_x * kr.V[:, :k] @ z1
+    y0 = kr.norm_x * kr.V[:, : k - d] @ z0
+    e1, e0, n1 = np.linalg.norm(y1 - ref), np.linalg.norm(y0 - ref), np.linalg.norm(y1)
+    slack = 1e-12 * n1
+    assert abs(e0 - e1) - slack <= est * n1 <= e0 + e1 + slack
