@@ -87,6 +87,10 @@ typedef struct ihipStream_t* nk_stream_t; /* a hipStream_t */
 #define NK_MLP_NTRAIN 9668
 #define NK_MLP_NPARAMS 9700
 
+/* inner basis of the nested method */
+#define NK_INNER_SAME 0
+#define NK_INNER_ARNOLDI 1
+
 /* two-pass lift */
 #define NK_TWO_PASS_AUTO 0 /* store V_k when it fits in device memory, else two passes */
 #define NK_TWO_PASS_ON 1   /* never store V_k: rebuild the basis in a second pass */
@@ -115,6 +119,11 @@ typedef struct nk_sign_params {
                         * 2: the same with each sweep of the basis replayed from a HIP graph
                         * captured on first use and cached on the handle; other cases, and 0,
                         * run the sources one after another */
+  int32_t inner;       /* basis of the nested method's inner space K_l(B, e_1) (Sec. 3, which
+                        * leaves it open): NK_INNER_SAME, the outer level's family with full
+                        * re-(bi)orthogonalisation (Lanczos at mu = 0, two-sided Lanczos
+                        * otherwise), or NK_INNER_ARNOLDI (orthonormal basis, Hessenberg H_l);
+                        * lockstep runs (block > 0) take NK_INNER_SAME only */
 } nk_sign_params;
 
 typedef struct nk_sign_info {
@@ -137,7 +146,8 @@ typedef struct nk_sign_info {
 
 /* Fill *p with defaults: m_w = -1, mu = 0, k = 100, ell = 0, tol = 0, nrhs = 1,
  * FP64, unscaled RH, two_pass AUTO, est_delay = 0, check_every = 50,
- * rh_maxit = 100, rh_tol = 1e-13, ell_per_rhs = NULL, profile = 0, block = 0. */
+ * rh_maxit = 100, rh_tol = 1e-13, ell_per_rhs = NULL, profile = 0, block = 0,
+ * inner = NK_INNER_SAME. */
 void nk_sign_params_default(nk_sign_params* p);
 
 /* Create a lattice context on the current HIP device.  dims = {Lx, Ly, Lz, Lt},

@@ -95,7 +95,8 @@ static int validate_params(nk_lattice* lat, const nk_sign_params* p) {
   }
   if (p->k < 1 || p->ell < 0 || p->nrhs < 1 || p->precision < 0 || p->precision > 2 || p->rh_maxit < 1 ||
       p->est_delay < 0 || p->est_delay >= p->k || !(p->tol >= 0.0) || p->two_pass < 0 || p->two_pass > 2 ||
-      p->rh_scaling < 0 || p->rh_scaling > 2 || p->profile < 0 || p->block < 0 || p->block > 2 || !std::isfinite(p->mu) || !std::isfinite(p->m_w)) {
+      p->rh_scaling < 0 || p->rh_scaling > 2 || p->profile < 0 || p->block < 0 || p->block > 2 || p->inner < 0 ||
+      p->inner > 1 || !std::isfinite(p->mu) || !std::isfinite(p->m_w)) {
     set_error("invalid sign parameters (k=%d ell=%d nrhs=%d precision=%d est_delay=%d)", p->k, p->ell, p->nrhs,
               p->precision, p->est_delay);
     return NK_EINVAL;
@@ -127,12 +128,12 @@ static int estimate(int kk, int ell, int herm, int d, const nk_sign_params* p, C
   std::vector<C64> z1(kk), z0(kk - d);
   SmallOut so;
   int e = small_sign_dev(kk, ell, herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling, p->rh_maxit, p->rh_tol,
-                         cb.z0, &so, st);
+                         cb.z0, &so, st, p->inner);
   if (e < 0) return e;
   NK_HIP(hipMemcpyAsync(z1.data(), cb.z0, kk * sizeof(C64), hipMemcpyDeviceToHost, st));
   NK_HIP(hipStreamSynchronize(st));
   e = small_sign_dev(kk - d, std::min(ell, kk - d), herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling,
-                     p->rh_maxit, p->rh_tol, cb.z0, &so, st);
+                     p->rh_maxit, p->rh_tol, cb.z0, &so, st, p->inner);
   if (e < 0) return e;
   NK_HIP(hipMemcpyAsync(z0.data(), cb.z0, (kk - d) * sizeof(C64), hipMemcpyDeviceToHost, st));
   NK_HIP(hipStreamSynchronize(st));
@@ -227,7 +228,7 @@ static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64
   }
   SmallOut so;
   int es = small_sign_dev(kused, std::min(ell, kused), herm, cb.c.alpha, cb.c.beta, cb.c.delta, p->rh_scaling,
-                          p->rh_maxit, p->rh_tol, cb.z, &so, st);
+                          p->rh_maxit, p->rh_tol, cb.z, &so, st, p->inner);
   if (es < 0) return es;
   if (es > 0 && warn == NK_OK) warn = es;
   if (p->est_delay > 0 && std::isnan(est) && kused - p->est_delay >= 1) {
@@ -534,8 +535,12 @@ int nk_small_sign(int32_t k, int32_t ell, int32_t hermitian, const double* alpha
   NK_HIP(hipMemcpy(a + k, beta, k * sizeof(C64), hipMemcpyHostToDevice));
   NK_HIP(hipMemcpy(a + 2 * k, delta, k * sizeof(C64), hipMemcpyHostToDevice));
   SmallOut so;
+  if (p->inner < 0 || p->inner > 1) {
+    set_error("invalid inner basis %d", p->inner);
+    return NK_EINVAL;
+  }
   int e = small_sign_dev(k, ell, hermitian, a, a + k, a + 2 * k, p->rh_scaling, p->rh_maxit, p->rh_tol, a + 3 * k,
-                         &so, nullptr);
+                         &so, nullptr, p->inner);
   if (e < 0) return e;
   NK_HIP(hipMemcpy(z, a + 3 * k, k * sizeof(C64), hipMemcpyDeviceToHost));
   if (info) {

@@ -620,7 +620,8 @@ static int block_range(nk_lattice* lat, const nk_sign_params* p, const int* ell,
 int block_sign(nk_lattice* lat, const nk_sign_params* p, const C64* x_canon, C64* y_canon, nk_sign_info* info,
                hipStream_t st) {
   const int r = p->nrhs, k = p->k;
-  if (p->mu == 0.0 || p->precision != NK_PREC_FP64 || p->tol > 0.0) return 1;  // not covered: one at a time
+  if (p->mu == 0.0 || p->precision != NK_PREC_FP64 || p->tol > 0.0 || p->inner != NK_INNER_SAME)
+    return 1;  // not covered: one at a time
   const size_t n = (size_t)12 * lat->g.V;
   std::vector<int> ell(r);
   for (int s = 0; s < r; ++s) ell[s] = std::min(p->ell_per_rhs ? p->ell_per_rhs[s] : p->ell, k);

@@ -284,7 +284,8 @@ struct SmallOut {
   bool inner_only = false; // stop after the inner projection (no Roberts-Higham, no lift)
 };
 int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,
-                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st);
+                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st,
+                   int inner = NK_INNER_SAME);
 
 // the inner projections of r problems at once (see small.hip)
 int small_inner_batch(int r, const int* k, const int* ell, int hermitian, const C64* const* alpha,

@@ -231,6 +231,8 @@ struct Inner {
   C64* b;
   C64* d;
   int* flags;
+  C64* hcol;     // [lmax][lmax] Arnoldi: column i of H_l at i * lmax (both passes summed)
+  int arnoldi;   // 1: one-sided recurrence on a general B, every coefficient kept
 };
 
 // the descriptor with its buffers seen as global memory (see as_global)
@@ -240,6 +242,8 @@ struct InnerG {
   gp<C64> V, W, u0, u1, q0, q1, part1, part2, a, b, d;  // u0/u1, q0/q1: the raw ping-pong vectors
   gp<double> part3;
   gp<int> flags;
+  gp<C64> hcol;
+  int arnoldi;
 };
 
 __device__ __forceinline__ InnerG inner_view(const Inner& s) {
@@ -264,6 +268,8 @@ __device__ __forceinline__ InnerG inner_view(const Inner& s) {
   g.b = as_global(s.b);
   g.d = as_global(s.d);
   g.flags = as_global(s.flags);
+  g.hcol = as_global(s.hcol);
+  g.arnoldi = s.arnoldi;
   return g;
 }
 
@@ -549,6 +555,11 @@ __global__ void __launch_bounds__(ST) k_in_sub(const Inner s0, const Inner* __re
   if (s.flags[0]) return;
   __syncthreads();
   if (!last && blockIdx.x == 0 && threadIdx.x == 0) stg(s.a + i, s.herm ? mk(s_c[0][i].re, 0.0) : s_c[0][i]);
+  if (s.arnoldi && blockIdx.x == 0)  // column i of H_l: the first pass stores, the second adds
+    for (int j = threadIdx.x; j <= i; j += ST) {
+      gp<C64> h = s.hcol + (size_t)i * s.lmax + j;
+      stg(h, last ? ldg(h) + s_c[0][j] : s_c[0][j]);
+    }
   // u -= V c, q -= W d: eight lanes per row, columns jl, jl + 8, ... of both
   // sides in one batch of loads
   const int rl = threadIdx.x >> 3, jl = threadIdx.x & 7;
@@ -649,6 +660,24 @@ __global__ void __launch_bounds__(ST) k_in_sub(const Inner s0, const Inner* __re
     for (int qq = 0; qq < 4; ++qq) s.part3[qq * s.nb2 + blockIdx.x] = v[qq];
 }
 
+// dense upper Hessenberg H_l (ld = l, row-major) of the Arnoldi option.
+// The recurrence subtracts b[c - 1] v_{c-1} from B v_c before it projects
+// (the Lanczos form), so the stored coefficient of v_{c-1} lacks b[c - 1]:
+// H[r][c] = hcol[c * lmax + r] (+ b[r] for r = c - 1) for r <= c,
+// H[c + 1][c] = |u_c| = d[c], else 0
+__global__ void k_hess_dense(int l, int lmax, const C64* __restrict__ hcol, const C64* __restrict__ b,
+                             const C64* __restrict__ d, C64* __restrict__ H) {
+  const size_t nn = (size_t)l * l;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / l), c = (int)(e % l);
+    C64 v = mk(0.0, 0.0);
+    if (r <= c) v = hcol[(size_t)c * lmax + r];
+    if (r + 1 == c) v = v + b[r];
+    if (r == c + 1) v = d[c];
+    H[e] = v;
+  }
+}
+
 // z = V y (k rows, l columns)
 __global__ void k_in_lift(int k, int l, const C64* __restrict__ V, const C64* __restrict__ S, int lds,
                           C64* __restrict__ z) {
@@ -697,6 +726,7 @@ static size_t inner_layout(int k, int ell, int hermitian, char* base, Inner* s, 
   const size_t oP1 = take((size_t)2 * nb1 * ell * sizeof(C64));
   const size_t oP2 = take((size_t)2 * nb2 * ell * sizeof(C64));
   const size_t oP3 = take((size_t)4 * nb2 * sizeof(double));
+  const size_t oHc = take((size_t)ell * ell * sizeof(C64));
   const size_t oI = take(8 * sizeof(int));
   if (!base) return bytes;
   s->k = k;
@@ -727,6 +757,8 @@ static size_t inner_layout(int k, int ell, int hermitian, char* base, Inner* s, 
   s->nb1 = nb1;
   s->nb2 = nb2;
   s->flags = (int*)(base + oI);
+  s->hcol = (C64*)(base + oHc);
+  s->arnoldi = 0;
   return bytes;
 }
 
@@ -748,9 +780,17 @@ static int inner_prepare(int k, int hermitian, const C64* alpha, const C64* beta
 }
 
 int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* beta, const C64* delta,
-                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st) {
+                   int rh_scaling, int rh_maxit, double rh_tol, C64* z, SmallOut* out, hipStream_t st, int inner) {
   if (k <= 0) return NK_EINVAL;
   if (ell > k) ell = k;
+  // Arnoldi runs the one-sided (Lanczos-form) recurrence on the general B and
+  // keeps every coefficient; its H_l is upper Hessenberg
+  const int arnoldi = inner == NK_INNER_ARNOLDI && ell > 0;
+  const int oneside = hermitian || arnoldi;
+  if (arnoldi && out && (out->hl_host || out->inner_only)) {
+    set_error("the tridiagonal H_l export is for the outer level's family only");
+    return NK_EINVAL;
+  }
   if (ell <= 0) {
     // non-nested: RH on dense H_k
     if (g_small.ensure((size_t)k * k * sizeof(C64))) return NK_ENOMEM;
@@ -775,19 +815,20 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     set_error("inner Krylov size %d exceeds %d", ell, LMAX);
     return NK_EINVAL;
   }
-  const size_t lay = inner_layout(k, ell, hermitian, nullptr, nullptr, nullptr);
+  const size_t lay = inner_layout(k, ell, oneside, nullptr, nullptr, nullptr);
   const size_t oS = (lay + 255) & ~(size_t)255;
   const size_t oD = oS + (((size_t)ell * ell * sizeof(C64) + 255) & ~(size_t)255);
   if (g_small.ensure(oD + 256)) return NK_ENOMEM;
   char* base = g_small.as<char>();
   Inner s;
   TriWork tw;
-  inner_layout(k, ell, hermitian, base, &s, &tw);
+  inner_layout(k, ell, oneside, base, &s, &tw);
+  s.arnoldi = arnoldi;
   C64* Hl = (C64*)(base + oS);
   Inner* sdev = (Inner*)(base + oD);
   NK_HIP(hipMemcpyAsync(sdev, &s, sizeof s, hipMemcpyHostToDevice, st));
-  if (int e = inner_prepare(k, hermitian, alpha, beta, delta, s, tw, st)) return e;
-  const int sides = hermitian ? 1 : 2;
+  if (int e = inner_prepare(k, oneside, alpha, beta, delta, s, tw, st)) return e;
+  const int sides = oneside ? 1 : 2;
   for (int i = 0; i < ell; ++i) {
     hipLaunchKernelGGL(k_in_gemv<false>, dim3(s.nb1, sides, 1), dim3(GR * 64), gemv_lds(i), st, s, nullptr, i);
     hipLaunchKernelGGL(k_in_sub<false>, dim3(s.nb2, 1, 1), dim3(ST), 0, st, s, nullptr, i, 0);
@@ -815,7 +856,10 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     out->ell_used = lu;
     return fl[0] ? NK_WARN_BREAKDOWN : NK_OK;
   }
-  hipLaunchKernelGGL(k_tri_dense, dim3(256), dim3(256), 0, st, lu, s.a, s.b, s.d, Hl);
+  if (arnoldi)
+    hipLaunchKernelGGL(k_hess_dense, dim3(256), dim3(256), 0, st, lu, ell, s.hcol, s.b, s.d, Hl);
+  else
+    hipLaunchKernelGGL(k_tri_dense, dim3(256), dim3(256), 0, st, lu, s.a, s.b, s.d, Hl);
   NK_HIP(hipGetLastError());
   int it = 0;
   double res = 0;

@@ -38,6 +38,8 @@ NK_MLP_STEPS = 4
 NK_MLP_NTRAIN = 9668
 NK_MLP_NPARAMS = 9700
 
+NK_INNER_SAME = 0
+NK_INNER_ARNOLDI = 1
 NK_TWO_PASS_AUTO = 0
 NK_TWO_PASS_ON = 1
 NK_TWO_PASS_OFF = 2
@@ -104,6 +106,7 @@ class nk_sign_params(C.Structure):
         ("ell_per_rhs", C.POINTER(C.c_int32)),
         ("profile", C.c_int32),
         ("block", C.c_int32),
+        ("inner", C.c_int32),
     ]
 
 
@@ -243,7 +246,10 @@ def nk_version() -> str:
 def nk_sign_params_default(**kw) -> nk_sign_params:
     p = nk_sign_params()
     library().nk_sign_params_default(C.byref(p))
+    names = {f[0] for f in nk_sign_params._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"nk_sign_params has no field {k!r}")
         if k == "ell_per_rhs":
             arr = (C.c_int32 * len(v))(*[int(e) for e in v])
             p._ell_keep = arr

@@ -185,6 +185,34 @@ def test_convergence_estimate_matches_oracle(cfg1, mu, ell):
     assert abs(info.est - ref) < 1e-6 * ref
 
 
+def test_arnoldi_inner_end_to_end(cfg1):
+    """The Arnoldi inner option through nk_sign_apply_device at 4^4, mu = 0.3
+    against the oracle at the same (k, l) (method level), and a lockstep
+    request with it runs the sources one at a time with the same result."""
+    lat, u, x = cfg1
+    b = nk()
+    mu, k, ell = 0.3, 150, 80
+    banner(f"4^4 mu={mu} k={k} l={ell} inner Arnoldi")
+    y, info, rc = _sign(lat, x, k=k, ell=ell, mu=mu, inner=b.NK_INNER_ARNOLDI)
+    assert rc == 0 and info.ell_used == ell
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    yo, _ = N.sign_apply(f, fd, x, k, ell, False, inner="arnoldi")
+    gold = np.load(os.path.join(GOLD, "sign_4x4x4x4_mu0.3_eps0.4.npy"))
+    eps_true = rel(yo, gold)
+    assert rel(y, yo) < max(1e-10, 10 * eps_true)
+    xs = latgen.random_sources(DIMS1, 2, 9)
+    p = b.nk_sign_params_default(k=k, ell=ell, mu=mu, nrhs=2, block=1, inner=b.NK_INNER_ARNOLDI)
+    dx = to_dev(xs)
+    dy = torch_cuda().empty_like(dx)
+    _, rc = b.nk_sign_apply_device(lat.h, p, dx, dy)
+    assert rc == 0
+    yb = to_host(dy).reshape(2, -1)
+    for r in range(2):
+        yr, _, _ = _sign(lat, xs[r], k=k, ell=ell, mu=mu, inner=b.NK_INNER_ARNOLDI)
+        assert rel(yb[r], yr) < 1e-14
+
+
 def test_ginsparg_wilson_on_gpu(cfg1):
     lat, u, x = cfg1
     banner("4^4 Ginsparg-Wilson relation of Dov")

@@ -100,6 +100,24 @@ def test_small_sign_matches_oracle(ritz, ell):
     assert info.rh_residual < 1e-9
 
 
+@pytest.mark.parametrize("ell", [1, 20, 45, 150])
+def test_small_sign_arnoldi_matches_oracle(ritz, ell):
+    """The Arnoldi inner option against the oracle's Arnoldi (Hessenberg H_l),
+    and at mu = 0, where B is Hermitian, against the Lanczos inner space."""
+    mu, H = ritz
+    herm = mu == 0.0
+    banner(f"small_sign arnoldi k={H.k} ell={ell} mu={mu}")
+    b = nk()
+    p = b.nk_sign_params_default(inner=b.NK_INNER_ARNOLDI)
+    z, info, rc = b.nk_small_sign(H.k, ell, herm, H.alpha, H.beta, H.delta, p)
+    zo, io = N.small_sign(H, ell, herm, inner="arnoldi")
+    assert rel(z, zo) < 1e-10
+    assert info.ell_used == min(ell, H.k)
+    if herm:
+        zs, _, _ = b.nk_small_sign(H.k, ell, herm, H.alpha, H.beta, H.delta)
+        assert rel(z, zs) < 1e-10
+
+
 def test_small_sign_ragged_k(ritz):
     mu, H = ritz
     herm = mu == 0.0

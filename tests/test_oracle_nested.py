@@ -169,3 +169,60 @@ def test_convergence_estimate_between_the_true_errors(k, d, ell):
     e1, e0, n1 = np.linalg.norm(y1 - ref), np.linalg.norm(y0 - ref), np.linalg.norm(y1)
     slack = 1e-12 * n1
     assert abs(e0 - e1) - slack <= est * n1 <= e0 + e1 + slack
+
+
+def _ritz(mu, k):
+    u, x, f, fd = _op((4, 4, 4, 4), mu, 0.6)
+    return N.outer_basis(f, fd, x.reshape(-1), k, mu == 0.0).H
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_arnoldi_relations(mu):
+    """The inner Arnoldi option: orthonormal V and H = V^dag B V (upper
+    Hessenberg), by matrix products rather than the recurrence."""
+    h = _ritz(mu, 80).dense()
+    b = h + np.linalg.solve(h, np.eye(h.shape[0]))
+    V, H = N.arnoldi(b, 30)
+    assert np.linalg.norm(V.conj().T @ V - np.eye(30)) < 1e-13
+    assert np.linalg.norm(V.conj().T @ b @ V - H) < 1e-12 * np.linalg.norm(b)
+    assert np.count_nonzero(np.tril(H, -2)) == 0
+
+
+def test_arnoldi_on_hermitian_b_is_lanczos():
+    """For Hermitian B the Arnoldi Hessenberg matrix is the Lanczos
+    tridiagonal one (two routes to the same H_l)."""
+    h = _ritz(0.0, 80).dense()
+    b = h + np.linalg.solve(h, np.eye(h.shape[0]))
+    _, H = N.arnoldi(b, 30)
+    L = N.inner_basis(b, 30, True).H.dense()
+    assert np.linalg.norm(H - L) < 1e-11 * np.linalg.norm(L)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_arnoldi_nested_at_full_inner_size_is_non_nested(mu):
+    H = _ritz(mu, 60)
+    z0, _ = N.small_sign(H, 0, mu == 0.0)
+    z1, _ = N.small_sign(H, 60, mu == 0.0, inner="arnoldi")
+    assert np.linalg.norm(z1 - z0) < 1e-10 * np.linalg.norm(z0)
+
+
+def test_arnoldi_nested_against_the_exact_sign():
+    """End to end at 4^4, mu = 0.3 (stored exact sign): the Arnoldi inner space
+    loses nothing against the plain method at l = 80 < k = 150 (whose error
+    is 2e-6 here), and agrees with the two-sided inner space to that error."""
+    import os
+
+    dims = (4, 4, 4, 4)
+    u = latgen.random_gauge(dims, 0.4, 0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sign_4x4x4x4_mu0.3_eps0.4.npy"))
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, 0.3).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -0.3).reshape(-1)
+    yp, _ = N.sign_apply(f, fd, x, 150, 0, False)
+    ya, _ = N.sign_apply(f, fd, x, 150, 80, False, inner="arnoldi")
+    ys, _ = N.sign_apply(f, fd, x, 150, 80, False)
+    ep = np.linalg.norm(yp.reshape(-1) - ref) / np.linalg.norm(ref)
+    ea = np.linalg.norm(ya.reshape(-1) - ref) / np.linalg.norm(ref)
+    assert ep < 1e-5
+    assert ea < 2.0 * ep
+    assert np.linalg.norm(ya - ys) < 2.0 * ep * np.linalg.norm(ys)
