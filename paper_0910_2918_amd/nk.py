@@ -443,6 +443,24 @@ def nk_sign_apply_device(h, params: nk_sign_params, x, y, stream=None):
     return info, rc
 
 
+def sign_apply(lat, x, mu: float = 0.0, k: int = 100, ell: int = 0, tol: float = 0.0, stream=None, **opts):
+    """y ~ sgn(gamma5 Dw(mu)) x for a contiguous complex128 CUDA tensor x holding
+    nrhs canonical vectors (nrhs = x.numel() / (12 V) of the Lattice lat);
+    other nk_sign_params fields as keywords.  Returns (y, info) with y a new
+    tensor shaped like x and the return code (0 or a positive warning) in
+    info.rc; a negative code raises NKError."""
+    import torch
+
+    V = lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3]
+    if x.numel() % (12 * V) != 0:
+        raise ValueError(f"x has {x.numel()} entries, not a multiple of 12 V = {12 * V}")
+    p = nk_sign_params_default(mu=mu, k=k, ell=ell, tol=tol, nrhs=x.numel() // (12 * V), **opts)
+    y = torch.empty_like(x)
+    info, rc = nk_sign_apply_device(lat.h, p, x, y, stream)
+    info.rc = rc
+    return y, info
+
+
 class Lattice:
     """Owns a lattice handle (context manager)."""
 

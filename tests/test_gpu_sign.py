@@ -213,6 +213,21 @@ def test_arnoldi_inner_end_to_end(cfg1):
         assert rel(yb[r], yr) < 1e-14
 
 
+def test_python_sign_apply_is_the_entry_point(cfg1):
+    """nk.sign_apply (tensor in, tensor and info out) gives the entry point's bits."""
+    lat, u, x = cfg1
+    b = nk()
+    banner("nk.sign_apply convenience call")
+    xs = to_dev(latgen.random_sources(DIMS1, 2, 4))
+    y, info = b.sign_apply(lat, xs, mu=0.3, k=80, ell=20)
+    assert info.rc == 0 and y.shape == xs.shape
+    y2 = torch_cuda().empty_like(xs)
+    b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(mu=0.3, k=80, ell=20, nrhs=2), xs, y2)
+    assert torch_cuda().equal(y, y2)
+    with pytest.raises(TypeError):
+        b.sign_apply(lat, xs, mu=0.3, k=80, no_such_field=1)
+
+
 def test_ginsparg_wilson_on_gpu(cfg1):
     lat, u, x = cfg1
     banner("4^4 Ginsparg-Wilson relation of Dov")
