@@ -382,6 +382,19 @@ def main() -> int:
 
     stencil = stencil_rates(torch, nk, latgen, dev, copy_gbs)
 
+    # the precision workload at its parameters (k = 1000, l = 200): each
+    # reduced-precision result against the FP64 one on the same source
+    precision = {"lattice": "16^4", "k": 1000, "ell": 200}
+    for mu_p in (0.0, MU):
+        y64 = torch.empty_like(x)
+        yp = torch.empty_like(x)
+        nk.nk_sign_apply_device(lat.h, nk.nk_sign_params_default(k=1000, ell=200, mu=mu_p, m_w=M_W), x, y64)
+        for prec, pname in ((nk.NK_PREC_FP32, "fp32"), (nk.NK_PREC_FP32_BF16LINKS, "fp32_bf16links")):
+            nk.nk_sign_apply_device(lat.h, nk.nk_sign_params_default(k=1000, ell=200, mu=mu_p, m_w=M_W,
+                                                                     precision=prec), x, yp)
+            precision[f"{pname}_mu{mu_p}_rel_err_vs_fp64"] = rel(yp, y64)
+        del y64, yp
+
     # the block stencil step: 32 sources in lockstep at 16^3 x 32 (plain,
     # k = 40), per source, beside the one-source kernel on the same lattice
     bdims, nsrc = (16, 16, 16, 32), 32
@@ -519,6 +532,7 @@ def main() -> int:
         "copy_GBps": copy_gbs,
         "step_kernels": step_kernels,
         "stencil": stencil,
+        "precision_vs_fp64": precision,
         "block_stencil": block_stencil,
         "batching_16x16x16x32": batching,
         "learned_scaling_24x24x24x24": rh24,

@@ -86,6 +86,48 @@ def test_method_level_nonhermitian(mu, k, ell):
     lat.close()
 
 
+def test_config2_accuracy_grid():
+    """The two-sided workload at its full size: 8^4, mu = 0.3, link width 0.6,
+    4 Gaussian sources in lockstep, k in {200, 400, 800} with l in {k/8, k/4},
+    against the non-nested run at k = 1500.  The plain error falls with k;
+    l = k/4 loses at most a factor 2 against the plain method at the same k
+    (Sec. 4: the inner space can be much smaller than the outer one); and one
+    sampled source at (200, 50) agrees with the oracle at the method level."""
+    b = nk()
+    dims, mu = (8, 8, 8, 8), 0.3
+    lat, u = make_lattice(dims, 0.6, seed=0)
+    xs = latgen.random_sources(dims, 4, 2)
+    dx = to_dev(xs)
+    torch = torch_cuda()
+
+    def run(k, ell):
+        dy = torch.empty_like(dx)
+        _, rc = b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=k, ell=ell, mu=mu, nrhs=4, block=1), dx, dy)
+        assert rc == b.NK_OK
+        return to_host(dy).reshape(4, -1)
+
+    banner("8^4 mu=0.3 r=4: reference k=1500 (non-nested)")
+    yref = run(1500, 0)
+    err = {}
+    for k in (200, 400, 800):
+        for ell in (0, k // 8, k // 4):
+            banner(f"8^4 mu=0.3 r=4 k={k} l={ell}")
+            y = run(k, ell)
+            err[(k, ell)] = max(rel(y[s], yref[s]) for s in range(4))
+    print("8^4 mu=0.3 max relative error over 4 sources:",
+          {f"k={k} l={e}": f"{v:.1e}" for (k, e), v in err.items()}, flush=True)
+    assert err[(200, 0)] > err[(400, 0)] > err[(800, 0)]
+    for k in (200, 400, 800):
+        assert err[(k, k // 4)] <= 2.0 * err[(k, 0)] + 1e-12
+    banner("8^4 source 0 at (200, 50) against the oracle")
+    f = lambda v: W.a_apply(u, v.reshape(xs[0].shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(xs[0].shape), M_W, -mu).reshape(-1)
+    yo, _ = N.sign_apply(f, fd, xs[0], 200, 50, False)
+    y0 = run(200, 50)[0]
+    assert rel(y0, yo) <= max(1e-10, 10 * rel(yo, yref[0]))
+    lat.close()
+
+
 @pytest.mark.parametrize("mu", [0.0, 0.3])
 def test_full_size_free_field_exact(mu):
     dims = (16, 16, 16, 16)
@@ -130,14 +172,17 @@ def test_two_pass_is_bit_identical(big):
     assert rel(y2, y1) < 1e-14
 
 
+@pytest.mark.parametrize("mu", [0.0, 0.3])
 @pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 5e-2)])
-def test_reduced_precision_error_is_stated(big, prec, tol):
+def test_reduced_precision_error_is_stated(big, prec, tol, mu):
+    """The precision workload at its parameters (16^4, link width 0.8, k = 1000,
+    l = 200): the FP32 and BF16-link results against the FP64 run, stated."""
     lat, x = big
-    banner(f"16^4 mu=0.3 precision={prec} vs FP64")
-    y64, _, _ = _sign(lat, x, k=300, ell=60, mu=0.3)
-    y, info, rc = _sign(lat, x, k=300, ell=60, mu=0.3, precision=prec)
+    banner(f"16^4 mu={mu} k=1000 l=200 precision={prec} vs FP64")
+    y64, _, _ = _sign(lat, x, k=1000, ell=200, mu=mu)
+    y, info, rc = _sign(lat, x, k=1000, ell=200, mu=mu, precision=prec)
     err = rel(y, y64)
-    print(f"precision {prec}: relative error vs FP64 = {err:.3e}")
+    print(f"precision {prec} mu={mu}: relative error vs FP64 = {err:.3e}")
     assert err < tol
 
 
