@@ -205,12 +205,14 @@ __global__ void k_tri_dense(int k, const C64* __restrict__ alpha, const C64* __r
 //  k_in_gemv : normalise the previous raw vectors (from partial sums), store
 //              v_i / w_i, u = B v_i - beta v_{i-1}, q = B^dag w_i - delta w_{i-1}
 //              (one wave per row), and the partial first-pass projections
-//              W^dag u, V^dag q over the block's four rows;
+//              W^dag u, V^dag q over the block's GR rows;
 //  k_in_sub  : reduce the partial projections, subtract (u -= V c, q -= W d;
 //              eight lanes per row), then emit either the partial projections
 //              of the second Gram-Schmidt pass or the partial sums of
 //              s = q^dag u, |u|^2, |q|^2 for the next normalisation.
 // V, W column-major (column j at j*k).  Hermitian: one side, W = V, q = u.
+// Arnoldi: the one-sided form on a general B, with every projection
+// coefficient kept (column i of the Hessenberg H_l, both passes summed).
 constexpr int GR = 16;  // rows per k_in_gemv block (one wave each, 1024 threads)
 constexpr int LMAX = 512;  // largest inner size (LDS of k_in_sub)
 constexpr int SR = 32;  // rows per k_in_sub block (eight lanes each)
