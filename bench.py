@@ -38,8 +38,9 @@ EPS = 0.8
 K1_BYTES_PER_SITE = 576 + 4 * 192 + 2 * 192
 # every PROFILE_EVERY-th outer step of each timed application has its two
 # kernels bracketed by HIP events bound to the launches (a sample: events on
-# every launch would slow the timed run itself by about 15%)
-PROFILE_EVERY = 10
+# every launch would slow the timed run itself by about 15%, on every tenth
+# step by about 0.7%)
+PROFILE_EVERY = 25
 HBM_PEAK_GBS = 8000.0
 PROFILE_PMC = os.path.join(ROOT, "profiles", "k_bil1_16x16x16x16_pmc.json")
 
@@ -210,7 +211,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--k", type=int, default=500)
-    ap.add_argument("--ell", type=int, default=84)
+    ap.add_argument("--ell", type=int, default=60)
     ap.add_argument("--kref-extra", type=int, default=500)
     ap.add_argument("--cpu-sample-steps", type=int, default=8)
     ap.add_argument("--batch", type=int, default=8, help="sources of the lockstep run")
