@@ -23,6 +23,16 @@ namespace nk {
 constexpr int ST = 256;
 
 __device__ __forceinline__ double cabs1s(C64 a) { return fabs(a.re) + fabs(a.im); }
+// 1 / b = conj(b) / |b|^2 with b first scaled by a power of two (exact) so
+// that |b|^2 neither overflows nor underflows: one division on the
+// recurrence's critical path instead of cdiv's four
+__device__ __forceinline__ C64 crecip(C64 b) {
+  int e;
+  (void)frexp(fmax(fabs(b.re), fabs(b.im)), &e);
+  const double br = ldexp(b.re, -e), bi = ldexp(b.im, -e);
+  const double q = 1.0 / (br * br + bi * bi);
+  return mk(ldexp(br * q, -e), ldexp(-bi * q, -e));
+}
 __device__ __forceinline__ C64 cdiv(C64 a, C64 b) {
   const double s = fmax(fabs(b.re), fabs(b.im));
   const double br = b.re / s, bi = b.im / s;
@@ -54,7 +64,7 @@ __device__ __forceinline__ void tri_lu_seq(int k, P al, P be, P de, C64* __restr
     const C64 p0 = sw ? b0 : a0, p1 = sw ? b1 : a1, p2 = sw ? b2 : a2;
     const C64 o0 = sw ? a0 : b0, o1 = sw ? a1 : b1, o2 = sw ? a2 : b2;
     if (!(cabs1s(p0) > 0.0)) bad = 1;
-    const C64 inv = cdiv(mk(1.0, 0.0), p0);
+    const C64 inv = crecip(p0);
     const C64 m = cmul(o0, inv);
     U0i[i] = inv;
     U1[i] = p1;
@@ -66,7 +76,7 @@ __device__ __forceinline__ void tri_lu_seq(int k, P al, P be, P de, C64* __restr
     a2 = z;
   }
   if (!(cabs1s(a0) > 0.0)) bad = 1;
-  U0i[k - 1] = cdiv(mk(1.0, 0.0), a0);
+  U0i[k - 1] = crecip(a0);
   U1[k - 1] = z;
   U2[k - 1] = z;
   if (k >= 2) U2[k - 2] = z;
