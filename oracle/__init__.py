@@ -20,6 +20,10 @@ subspace method for the overlap operator", PoS LATTICE2009):
 * ``nested``   -- the non-nested approximation, Eq. (3) with Eq. (4), and the
                   nested approximation, Eq. (5), with the preconditioning step
                   H_k -> H_k + H_k^{-1} of Eq. (6); the convergence estimate.
+* ``deflation``-- exact treatment of m critical eigenvalues (Sec. 2): the
+                  exact part R_m sgn(Lambda_m) L_m^dag x plus the Krylov
+                  approximation on the projected source; dense critical
+                  eigenpairs for small lattices.
 * ``freefield``-- closed form of the free-field (U = 1) operator in momentum
                   space, an exact reference at any volume.
 
