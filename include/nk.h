@@ -296,6 +296,37 @@ int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, dou
 int nk_sign_apply_device(nk_lattice* lat, const nk_sign_params* p, const void* x, void* y,
                          nk_sign_info* info, nk_stream_t stream);
 
+/* Largest number of deflated eigenpairs nk_sign_apply_deflated_device takes. */
+#define NK_DEFL_MAX 1024
+
+/* y ~ sgn(gamma5 Dw(mu)) x with m critical eigenvalues treated exactly
+ * (deflation, Sec. 2): with right eigenvectors R = [r_1 .. r_m]
+ * (A r_i = lambda_i r_i), left eigenvectors L = [l_1 .. l_m]
+ * (l_i^dag A = lambda_i l_i^dag) and L^dag R = I,
+ *   y = R sgn(Lambda) (L^dag x) + [Krylov approximation of sgn(A)] (x - R L^dag x),
+ * where the Krylov part is exactly what nk_sign_apply_device computes with the
+ * same parameters (nested for ell > 0, non-nested for ell = 0), applied to the
+ * projected source.  sgn(lambda) = sgn(Re lambda).  At mu = 0 (Hermitian A)
+ * pass L = R with orthonormal columns.
+ *   lam  host, 2 m doubles: the eigenvalues, (re, im) interleaved; only the
+ *        sign of the real part is used, and a zero or non-finite entry is
+ *        NK_EINVAL;
+ *   R, L device complex128, m canonical vectors each, one after another
+ *        (column i at offset i * 12 V); the library does not check that they
+ *        are eigenvectors or that L^dag R = I: the result is exact only when
+ *        they are;
+ *   x, y device complex128, p->nrhs canonical vectors; the same eigenpairs
+ *        serve every source.  y must not overlap x, R or L.
+ * 0 <= m <= NK_DEFL_MAX; m = 0 is nk_sign_apply_device.  A source whose
+ * projection is exactly zero (x in the span of R) gets only the exact part,
+ * and runs no Krylov iteration.  Workspace (p->nrhs projected sources and the
+ * projections) is kept in the handle.  Synchronises `stream` before
+ * returning; info as for nk_sign_apply_device (zeroed if no source needed the
+ * Krylov part). */
+int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int32_t m, const double* lam,
+                                  const void* R, const void* L, const void* x, void* y, nk_sign_info* info,
+                                  nk_stream_t stream);
+
 /* Launch shape of the blocked Gauss-Jordan inverse inside Roberts-Higham for
  * matrices of order > 128 (Eq. (4)): panel threads (256, 512 or 1024) x rows
  * per thread (1, 2 or 4; their product must cover the order) and the update

@@ -291,6 +291,7 @@ nk_lattice::~nk_lattice() {
   tmp.release();
   bvec.release();
   bsmall.release();
+  defl.release();
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
 }
 
@@ -718,6 +719,101 @@ int nk_sign_apply_device(nk_lattice* lat, const nk_sign_params* p, const void* x
     if (e < 0) return e;
     if (e > worst) worst = e;
   }
+  return worst;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int32_t m, const double* lam,
+                                  const void* R, const void* L, const void* x, void* y, nk_sign_info* info,
+                                  nk_stream_t stream) {
+  if (int e = validate_params(lat, p)) return e;
+  if (m < 0 || m > NK_DEFL_MAX) {
+    set_error("m = %d deflated eigenpairs outside [0, %d]", m, NK_DEFL_MAX);
+    return NK_EINVAL;
+  }
+  if (m == 0) return nk_sign_apply_device(lat, p, x, y, info, stream);
+  const size_t n = (size_t)12 * lat->g.V;
+  const size_t vb = (size_t)p->nrhs * n * sizeof(C64), cb = (size_t)m * n * sizeof(C64);
+  if (!lam || !R || !L || !x || !y || overlaps(y, vb, x, vb) || overlaps(y, vb, R, cb) || overlaps(y, vb, L, cb)) {
+    set_error("invalid deflation arguments (NULL, or y overlapping x, R or L)");
+    return NK_EINVAL;
+  }
+  DeflSigns neg{};
+  for (int i = 0; i < m; ++i) {
+    const double re = lam[2 * i], im = lam[2 * i + 1];
+    if (!std::isfinite(re) || !std::isfinite(im) || re == 0.0) {
+      set_error("eigenvalue %d = (%g, %g): sgn needs a finite value off the imaginary axis", i, re, im);
+      return NK_EINVAL;
+    }
+    if (re < 0.0) neg.w[i >> 6] |= 1ull << (i & 63);
+  }
+  for (int r = 0; r < p->nrhs; ++r) {
+    const int ell = p->ell_per_rhs ? p->ell_per_rhs[r] : p->ell;
+    if (ell < 0 || ell > p->k) {
+      set_error("ell_per_rhs[%d] = %d outside [0, k]", r, ell);
+      return NK_EINVAL;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = defl_partials(n);
+  const size_t npart = (size_t)m * nb, nc = (size_t)p->nrhs * (m + 1);
+  if (lat->defl.ensure((npart + nc + (size_t)p->nrhs * n) * sizeof(C64))) return NK_ENOMEM;
+  C64* part = lat->defl.as<C64>();
+  C64* c = part + npart;         // [nrhs][m] projections, then [nrhs] squared norms
+  C64* nrm = c + (size_t)p->nrhs * m;
+  C64* xp = nrm + p->nrhs;       // [nrhs][n] projected sources
+  const C64* Rd = (const C64*)R;
+  const C64* Ld = (const C64*)L;
+  for (int r = 0; r < p->nrhs; ++r) {
+    const C64* xr = (const C64*)x + r * n;
+    C64* xpr = xp + r * n;
+    if (int e = defl_dots(Ld, m, n, xr, part, c + (size_t)r * m, st)) return e;
+    if (int e = defl_combine(Rd, m, n, c + (size_t)r * m, neg, 0, xr, xpr, st)) return e;
+    if (int e = defl_dots(xpr, 1, n, xpr, part, nrm + r, st)) return e;
+  }
+  std::vector<C64> hn(p->nrhs);
+  NK_HIP(hipMemcpyAsync(hn.data(), nrm, p->nrhs * sizeof(C64), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));
+  bool all = true;
+  for (int r = 0; r < p->nrhs; ++r) {
+    if (!std::isfinite(hn[r].re)) {
+      set_error("source %d is not finite", r);
+      return NK_EINVAL;
+    }
+    all = all && hn[r].re > 0.0;
+  }
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->est = std::numeric_limits<double>::quiet_NaN();
+  }
+  int worst = NK_OK;
+  if (all) {
+    worst = nk_sign_apply_device(lat, p, xp, y, info, stream);
+    if (worst < 0) return worst;
+  } else {
+    for (int r = 0; r < p->nrhs; ++r) {
+      C64* yr = (C64*)y + r * n;
+      if (!(hn[r].re > 0.0)) {
+        NK_HIP(hipMemsetAsync(yr, 0, n * sizeof(C64), st));
+        continue;
+      }
+      nk_sign_params q = *p;
+      q.nrhs = 1;
+      q.ell = p->ell_per_rhs ? p->ell_per_rhs[r] : p->ell;
+      q.ell_per_rhs = nullptr;
+      const int e = nk_sign_apply_device(lat, &q, xp + r * n, yr, info, stream);
+      if (e < 0) return e;
+      if (e > worst) worst = e;
+    }
+  }
+  for (int r = 0; r < p->nrhs; ++r)
+    if (int e = defl_combine(Rd, m, n, c + (size_t)r * m, neg, 1, nullptr, (C64*)y + r * n, st)) return e;
+  NK_HIP(hipStreamSynchronize(st));
   return worst;
 }
 

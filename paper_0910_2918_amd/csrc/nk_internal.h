@@ -202,6 +202,7 @@ struct nk_lattice {
   nk::DevBuf tmp;      // device-layout temporaries of the stand-alone operator calls
   nk::DevBuf bvec;     // multi-source path: per-source vectors (basis, W ring, p, q, x, y)
   nk::DevBuf bsmall;   // multi-source path: coefficients, partial sums, small problems
+  nk::DevBuf defl;     // deflation: partial sums, projections, projected sources
   // multi-source path: sweeps captured as HIP graphs, keyed by their launch arguments
   struct Graph {
     std::vector<char> key;
@@ -223,6 +224,18 @@ struct nk_lattice {
 namespace nk {
 
 // ----- launchers implemented in the .hip files ------------------------------
+// deflation.hip: bit i set = eigenvalue i has negative real part
+struct DeflSigns {
+  uint64_t w[NK_DEFL_MAX / 64];
+};
+int defl_partials(size_t n);
+// c[i] = a_i^dag x for the m columns a_i (each n entries, one after another);
+// part holds m * defl_partials(n) partial sums
+int defl_dots(const C64* a, int m, size_t n, const C64* x, C64* part, C64* c, hipStream_t st);
+// mode 0: out = x - R c; mode 1: out += R sgn(Lambda) c
+int defl_combine(const C64* r, int m, size_t n, const C64* c, const DeflSigns& neg, int mode, const C64* x, C64* out,
+                 hipStream_t st);
+
 // layout.hip
 int pack_gauge(nk_lattice* lat, const C64* canon, hipStream_t st);
 template <class R>

@@ -38,6 +38,8 @@ NK_MLP_STEPS = 4
 NK_MLP_NTRAIN = 9668
 NK_MLP_NPARAMS = 9700
 
+NK_DEFL_MAX = 1024
+
 NK_INNER_SAME = 0
 NK_INNER_ARNOLDI = 1
 NK_TWO_PASS_AUTO = 0
@@ -70,6 +72,7 @@ EXPORTS = (
     "nk_adam_step_device",
     "nk_sign_apply",
     "nk_sign_apply_device",
+    "nk_sign_apply_deflated_device",
     "nk_stencil_groups",
     "nk_rh_tile_force",
     "nk_rh_tile_choice",
@@ -175,6 +178,8 @@ def library():
         "nk_adam_step_device": (C.c_int, [i32, vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
         "nk_sign_apply": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info)]),
         "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
+        "nk_sign_apply_deflated_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, vp, vp,
+                                                    P(nk_sign_info), vp]),
         "nk_stencil_groups": (C.c_int, [vp, i32, i32]),
         "nk_rh_tile_force": (C.c_int, [i32, i32, i32]),
         "nk_rh_tile_choice": (C.c_int, [i32, i32, P(i32)]),
@@ -443,6 +448,17 @@ def nk_sign_apply_device(h, params: nk_sign_params, x, y, stream=None):
     return info, rc
 
 
+def nk_sign_apply_deflated_device(h, params: nk_sign_params, lam, R, L, x, y, stream=None):
+    """Device tensors x, y, R, L (R and L hold m canonical vectors each) and
+    host eigenvalues lam (m complex); returns (info, rc)."""
+    lam = np.ascontiguousarray(lam, dtype=np.complex128).reshape(-1)
+    m = int(lam.size)
+    info = nk_sign_info()
+    rc = _check(library().nk_sign_apply_deflated_device(h, C.byref(params), m, _hptr(lam), _dptr(R), _dptr(L),
+                                                        _dptr(x), _dptr(y), C.byref(info), _stream(stream)))
+    return info, rc
+
+
 def sign_apply(lat, x, mu: float = 0.0, k: int = 100, ell: int = 0, tol: float = 0.0, stream=None, **opts):
     """y ~ sgn(gamma5 Dw(mu)) x for a contiguous complex128 CUDA tensor x holding
     nrhs canonical vectors (nrhs = x.numel() / (12 V) of the Lattice lat);
@@ -457,6 +473,26 @@ def sign_apply(lat, x, mu: float = 0.0, k: int = 100, ell: int = 0, tol: float =
     p = nk_sign_params_default(mu=mu, k=k, ell=ell, tol=tol, nrhs=x.numel() // (12 * V), **opts)
     y = torch.empty_like(x)
     info, rc = nk_sign_apply_device(lat.h, p, x, y, stream)
+    info.rc = rc
+    return y, info
+
+
+def sign_apply_deflated(lat, x, lam, R, L, mu: float = 0.0, k: int = 100, ell: int = 0, tol: float = 0.0,
+                        stream=None, **opts):
+    """sign_apply with the eigenpairs (lam, R, L) treated exactly: lam host
+    complex (m,), R and L contiguous complex128 CUDA tensors of m canonical
+    vectors each with L^dag R = I.  Returns (y, info) like sign_apply."""
+    import torch
+
+    V = lat.dims[0] * lat.dims[1] * lat.dims[2] * lat.dims[3]
+    if x.numel() % (12 * V) != 0:
+        raise ValueError(f"x has {x.numel()} entries, not a multiple of 12 V = {12 * V}")
+    m = int(np.asarray(lam).size)
+    if R.numel() != m * 12 * V or L.numel() != m * 12 * V:
+        raise ValueError(f"R and L must hold m = {m} vectors of 12 V = {12 * V} entries")
+    p = nk_sign_params_default(mu=mu, k=k, ell=ell, tol=tol, nrhs=x.numel() // (12 * V), **opts)
+    y = torch.empty_like(x)
+    info, rc = nk_sign_apply_deflated_device(lat.h, p, lam, R, L, x, y, stream)
     info.rc = rc
     return y, info
 
