@@ -24,6 +24,9 @@ subspace method for the overlap operator", PoS LATTICE2009):
                   exact part R_m sgn(Lambda_m) L_m^dag x plus the Krylov
                   approximation on the projected source; dense critical
                   eigenpairs for small lattices.
+* ``overlap``  -- Dov(mu) = 1 + gamma5 sgn(gamma5 Dw(mu)) (Eq. (1)), its
+                  adjoint, and CG on the normal equations (CGNR) to solve
+                  Dov y = b.
 * ``freefield``-- closed form of the free-field (U = 1) operator in momentum
                   space, an exact reference at any volume.
 
