@@ -327,6 +327,33 @@ int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int3
                                   const void* R, const void* L, const void* x, void* y, nk_sign_info* info,
                                   nk_stream_t stream);
 
+/* The overlap operator (Sec. 1, Eq. (1)) on p->nrhs canonical device vectors:
+ *   dagger = 0: y = Dov(mu) x = x + gamma5 sgn(gamma5 Dw(mu)) x;
+ *   dagger = 1: y = Dov(mu)^dag x = x + sgn(gamma5 Dw(-mu)) gamma5 x
+ * (sgn(A)^dag = sgn(A^dag) and A^dag = gamma5 Dw(-mu)), with the sign
+ * computed by nk_sign_apply_device with the parameters p (nested for
+ * ell > 0), so the same errors and warnings apply, a zero source included.
+ * gamma5 = diag(1, 1, -1, -1) on the spin index.  x and y must not overlap;
+ * one temporary of the size of x is kept in the handle.  Synchronises
+ * `stream` before returning; info describes the sign application. */
+int nk_overlap_apply_device(nk_lattice* lat, const nk_sign_params* p, int32_t dagger, const void* x, void* y,
+                            nk_sign_info* info, nk_stream_t stream);
+
+/* Solve Dov(mu) y = b for one canonical device vector b (p->nrhs must be 1)
+ * by the conjugate-gradient method on the normal equations
+ * Dov^dag Dov y = Dov^dag b (CGNR), from y = 0, with Dov and Dov^dag applied
+ * as nk_overlap_apply_device does (two sign applications per iteration).
+ * Stops when the recursively updated residual |b - Dov y| <= tol |b| or after
+ * maxit iterations (NK_WARN_NOTCONV, y the last iterate).  The attainable
+ * residual is bounded by the sign's own accuracy at (k, ell).  b = 0 gives
+ * y = 0 with *iters = 0.  Writes the iterations and the final relative
+ * residual to *iters, *resid.  Returns the largest warning of the sign
+ * applications or NK_WARN_NOTCONV; tol <= 0, maxit < 1, nrhs != 1 or b and y
+ * overlapping are NK_EINVAL.  Workspace (five vectors) is kept in the handle;
+ * synchronises `stream` before returning. */
+int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, double tol, int32_t maxit, const void* b,
+                            void* y, int32_t* iters, double* resid, nk_stream_t stream);
+
 /* Launch shape of the blocked Gauss-Jordan inverse inside Roberts-Higham for
  * matrices of order > 128 (Eq. (4)): panel threads (256, 512 or 1024) x rows
  * per thread (1, 2 or 4; their product must cover the order) and the update

@@ -292,6 +292,7 @@ nk_lattice::~nk_lattice() {
   bvec.release();
   bsmall.release();
   defl.release();
+  ovl.release();
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
 }
 
@@ -815,6 +816,39 @@ int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int3
     if (int e = defl_combine(Rd, m, n, c + (size_t)r * m, neg, 1, nullptr, (C64*)y + r * n, st)) return e;
   NK_HIP(hipStreamSynchronize(st));
   return worst;
+}
+
+int nk_overlap_apply_device(nk_lattice* lat, const nk_sign_params* p, int32_t dagger, const void* x, void* y,
+                            nk_sign_info* info, nk_stream_t stream) {
+  if (int e = validate_params(lat, p)) return e;
+  const size_t n = (size_t)12 * lat->g.V * p->nrhs;
+  if (!x || !y || overlaps(x, n * sizeof(C64), y, n * sizeof(C64)) || (dagger != 0 && dagger != 1)) {
+    set_error("invalid overlap arguments (NULL, overlapping x and y, or dagger not 0/1)");
+    return NK_EINVAL;
+  }
+  if (lat->ovl.ensure(n * sizeof(C64))) return NK_ENOMEM;
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->est = std::numeric_limits<double>::quiet_NaN();
+  }
+  return overlap_apply(lat, p, dagger, (const C64*)x, (C64*)y, lat->ovl.as<C64>(), info, (hipStream_t)stream);
+}
+
+int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, double tol, int32_t maxit, const void* b,
+                            void* y, int32_t* iters, double* resid, nk_stream_t stream) {
+  if (int e = validate_params(lat, p)) return e;
+  const size_t n = (size_t)12 * lat->g.V;
+  if (p->nrhs != 1 || !(tol > 0.0) || !std::isfinite(tol) || maxit < 1 || !b || !y || !iters || !resid ||
+      overlaps(b, n * sizeof(C64), y, n * sizeof(C64))) {
+    set_error("invalid overlap-solve arguments (nrhs must be 1, tol > 0, maxit >= 1, b and y apart)");
+    return NK_EINVAL;
+  }
+  int it = 0;
+  double res = 0.0;
+  const int e = overlap_solve(lat, p, tol, maxit, (const C64*)b, (C64*)y, &it, &res, (hipStream_t)stream);
+  *iters = it;
+  *resid = res;
+  return e;
 }
 
 int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, double* y, nk_sign_info* info) {

@@ -203,6 +203,7 @@ struct nk_lattice {
   nk::DevBuf bvec;     // multi-source path: per-source vectors (basis, W ring, p, q, x, y)
   nk::DevBuf bsmall;   // multi-source path: coefficients, partial sums, small problems
   nk::DevBuf defl;     // deflation: partial sums, projections, projected sources
+  nk::DevBuf ovl;      // overlap operator and solver: CG vectors, sign temporaries
   // multi-source path: sweeps captured as HIP graphs, keyed by their launch arguments
   struct Graph {
     std::vector<char> key;
@@ -232,6 +233,12 @@ int defl_partials(size_t n);
 // c[i] = a_i^dag x for the m columns a_i (each n entries, one after another);
 // part holds m * defl_partials(n) partial sums
 int defl_dots(const C64* a, int m, size_t n, const C64* x, C64* part, C64* c, hipStream_t st);
+// overlap.hip: y = Dov x (dagger = 0) or Dov^dag x, p->nrhs sources, tmp as
+// large as x; CGNR for Dov y = b (one source)
+int overlap_apply(nk_lattice* lat, const nk_sign_params* p, int dagger, const C64* x, C64* y, C64* tmp,
+                  nk_sign_info* info, hipStream_t st);
+int overlap_solve(nk_lattice* lat, const nk_sign_params* p, double tol, int maxit, const C64* b, C64* y,
+                  int* iters, double* resid, hipStream_t st);
 // mode 0: out = x - R c; mode 1: out += R sgn(Lambda) c
 int defl_combine(const C64* r, int m, size_t n, const C64* c, const DeflSigns& neg, int mode, const C64* x, C64* out,
                  hipStream_t st);

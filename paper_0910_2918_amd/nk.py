@@ -73,6 +73,8 @@ EXPORTS = (
     "nk_sign_apply",
     "nk_sign_apply_device",
     "nk_sign_apply_deflated_device",
+    "nk_overlap_apply_device",
+    "nk_overlap_solve_device",
     "nk_stencil_groups",
     "nk_rh_tile_force",
     "nk_rh_tile_choice",
@@ -180,6 +182,9 @@ def library():
         "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
         "nk_sign_apply_deflated_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, vp, vp,
                                                     P(nk_sign_info), vp]),
+        "nk_overlap_apply_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, P(nk_sign_info), vp]),
+        "nk_overlap_solve_device": (C.c_int, [vp, P(nk_sign_params), C.c_double, i32, vp, vp, P(i32),
+                                              P(C.c_double), vp]),
         "nk_stencil_groups": (C.c_int, [vp, i32, i32]),
         "nk_rh_tile_force": (C.c_int, [i32, i32, i32]),
         "nk_rh_tile_choice": (C.c_int, [i32, i32, P(i32)]),
@@ -457,6 +462,23 @@ def nk_sign_apply_deflated_device(h, params: nk_sign_params, lam, R, L, x, y, st
     rc = _check(library().nk_sign_apply_deflated_device(h, C.byref(params), m, _hptr(lam), _dptr(R), _dptr(L),
                                                         _dptr(x), _dptr(y), C.byref(info), _stream(stream)))
     return info, rc
+
+
+def nk_overlap_apply_device(h, params: nk_sign_params, dagger: bool, x, y, stream=None):
+    """y = Dov x or Dov^dag x on device tensors; returns (info, rc)."""
+    info = nk_sign_info()
+    rc = _check(library().nk_overlap_apply_device(h, C.byref(params), 1 if dagger else 0, _dptr(x), _dptr(y),
+                                                  C.byref(info), _stream(stream)))
+    return info, rc
+
+
+def nk_overlap_solve_device(h, params: nk_sign_params, tol: float, maxit: int, b, y, stream=None):
+    """CGNR for Dov y = b on device tensors; returns (iterations, relative residual, rc)."""
+    it = C.c_int32(0)
+    res = C.c_double(0.0)
+    rc = _check(library().nk_overlap_solve_device(h, C.byref(params), float(tol), int(maxit), _dptr(b), _dptr(y),
+                                                  C.byref(it), C.byref(res), _stream(stream)))
+    return it.value, res.value, rc
 
 
 def sign_apply(lat, x, mu: float = 0.0, k: int = 100, ell: int = 0, tol: float = 0.0, stream=None, **opts):

@@ -1,0 +1,136 @@
+"""GPU parity of the overlap operator (Eq. (1)) and the CGNR solver on it.
+
+* Dov and Dov^dag on a 2x2x4x4 lattice against the dense Dov built from the
+  exact sign (Schur route), at a k where the sign's Krylov error is below
+  1e-12 (4e-13 at mu = 0.3 in the oracle): <= 1e-9;
+* at 16^4 (the benchmark lattice, k = 500, l = 60): the adjoint identity
+  <u, Dov v> = <Dov^dag u, v> and Ginsparg-Wilson, to the sign's accuracy;
+* CGNR against np.linalg.solve on the dense Dov (2x2x4x4), and at 16^4 a
+  solve whose true residual is checked with an independent application;
+* edge cases: b = 0, an iteration cap, invalid arguments.
+"""
+import numpy as np
+import pytest
+
+import latgen
+from oracle import dense as D
+from oracle import overlap as O
+from oracle import wilson as W
+from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(**kw):
+    return nk().nk_sign_params_default(m_w=M_W, **kw)
+
+
+def _apply(lat, x, dagger, **kw):
+    dx = to_dev(x)
+    dy = torch_cuda().empty_like(dx)
+    info, rc = nk().nk_overlap_apply_device(lat.h, _params(**kw), dagger, dx, dy)
+    return to_host(dy), rc
+
+
+def _cdot(a, b):
+    return complex(np.vdot(np.ravel(a), np.ravel(b)))
+
+
+@pytest.fixture(scope="module", params=[0.0, 0.3])
+def small(request):
+    mu = request.param
+    dims = (2, 2, 4, 4)
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    xs = latgen.random_sources(dims, 2, 1)
+    dov = O.dense_dov(D.sign_schur(W.dense_matrix(u, M_W, mu)))
+    yield mu, lat, xs, dov
+    lat.close()
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+def test_apply_matches_dense(small, dagger):
+    mu, lat, xs, dov = small
+    banner(f"overlap apply 2x2x4x4 mu={mu} dagger={dagger} k=400")
+    y, rc = _apply(lat, xs[0], dagger, mu=mu, k=400, ell=0)
+    ref = (dov.conj().T if dagger else dov) @ xs[0].reshape(-1)
+    assert rc == 0
+    assert rel(y, ref) < 1e-9
+
+
+def test_solve_matches_dense(small):
+    mu, lat, xs, dov = small
+    banner(f"overlap CGNR 2x2x4x4 mu={mu} k=400")
+    b = nk()
+    db = to_dev(xs[1])
+    dy = torch_cuda().empty_like(db)
+    it, res, rc = b.nk_overlap_solve_device(lat.h, _params(mu=mu, k=400, ell=0), 1e-11, 100, db, dy)
+    assert rc == 0 and res <= 1e-11 and 5 <= it <= 40
+    y = to_host(dy)
+    assert rel(y, np.linalg.solve(dov, xs[1].reshape(-1))) < 1e-9
+    # the oracle's CGNR on the dense operator takes about as many steps
+    _, it_o, _, _ = O.cgnr(lambda v: dov @ v, lambda v: dov.conj().T @ v, xs[1].reshape(-1), 1e-11, 100)
+    assert abs(it - it_o) <= 2
+
+
+def test_solve_edge_cases(small):
+    mu, lat, xs, dov = small
+    b = nk()
+    p = _params(mu=mu, k=200, ell=0)
+    db = to_dev(np.zeros_like(xs[0]))
+    dy = torch_cuda().empty_like(db)
+    dy.fill_(1.0)
+    it, res, rc = b.nk_overlap_solve_device(lat.h, p, 1e-8, 10, db, dy)
+    assert (it, rc) == (0, 0) and not np.any(to_host(dy))
+    db = to_dev(xs[0])
+    it, res, rc = b.nk_overlap_solve_device(lat.h, p, 1e-12, 1, db, dy)
+    assert it == 1 and rc == b.NK_WARN_NOTCONV and 0 < res < 1
+    for bad in (dict(tol=0.0, maxit=10), dict(tol=1e-8, maxit=0)):
+        with pytest.raises(b.NKError) as ei:
+            b.nk_overlap_solve_device(lat.h, p, bad["tol"], bad["maxit"], db, dy)
+        assert ei.value.code == b.NK_EINVAL
+    with pytest.raises(b.NKError) as ei:
+        b.nk_overlap_solve_device(lat.h, _params(mu=mu, k=200, ell=0, nrhs=2), 1e-8, 10,
+                                  to_dev(xs), torch_cuda().empty_like(to_dev(xs)))
+    assert ei.value.code == b.NK_EINVAL
+    with pytest.raises(b.NKError) as ei:
+        b.nk_overlap_apply_device(lat.h, p, False, db, db)
+    assert ei.value.code == b.NK_EINVAL
+
+
+@pytest.fixture(scope="module")
+def big():
+    dims = (16, 16, 16, 16)
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    xs = latgen.random_sources(dims, 2, 0)
+    yield lat, xs
+    lat.close()
+
+
+def test_full_size_adjoint_and_ginsparg_wilson(big):
+    lat, xs = big
+    banner("overlap 16^4 mu=0.3 k=500 l=60: adjoint and Ginsparg-Wilson")
+    kw = dict(mu=0.3, k=500, ell=60)
+    u, v = xs
+    dv, _ = _apply(lat, v, False, **kw)
+    du, _ = _apply(lat, u, True, **kw)
+    lhs, rhs = _cdot(u, dv), _cdot(du, v)
+    scale = np.linalg.norm(u) * np.linalg.norm(v)
+    assert abs(lhs - rhs) < 1e-7 * scale
+    g5v = O.gamma5(v)
+    a, _ = _apply(lat, g5v, False, **kw)  # Dov g5 v
+    gw_l = O.gamma5(dv) + a  # g5 Dov v + Dov g5 v
+    gw_r, _ = _apply(lat, O.gamma5(dv.reshape(v.shape)), False, **kw)  # Dov g5 Dov v
+    assert rel(gw_l, gw_r) < 1e-7
+
+
+def test_full_size_solve(big):
+    lat, xs = big
+    banner("overlap CGNR 16^4 mu=0.3 k=500 l=60 tol=1e-7")
+    b = nk()
+    kw = dict(mu=0.3, k=500, ell=60)
+    db = to_dev(xs[0])
+    dy = torch_cuda().empty_like(db)
+    it, res, rc = b.nk_overlap_solve_device(lat.h, _params(**kw), 1e-7, 100, db, dy)
+    assert rc == 0 and res <= 1e-7 and it < 60
+    dr, _ = _apply(lat, to_host(dy).reshape(xs[0].shape), False, **kw)
+    assert rel(dr, xs[0]) < 1e-6
