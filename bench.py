@@ -397,6 +397,26 @@ def main() -> int:
                  "overhead_GBps": defl_bytes / max(t_over, 1e-9) / 1e9}
     del rd, ld
 
+    # the overlap operator of Eq. (1) in a linear solve: CGNR for Dov y = b at
+    # the same (k, l), two sign applications per iteration; the true residual
+    # is checked with one more application
+    b_ov = torch.from_numpy(latgen.random_sources(DIMS, 1, 8)[0].reshape(-1)).to(dev)
+    y_ov = torch.empty_like(b_ov)
+    r_ov = torch.empty_like(b_ov)
+    p_ov = params(args.k, args.ell, scaling=LEARNED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_ov, res_ov, rc_ov = nk.nk_overlap_solve_device(lat.h, p_ov, 1e-7, 200, b_ov, y_ov)
+    torch.cuda.synchronize()
+    t_ov = time.perf_counter() - t0
+    nk.nk_overlap_apply_device(lat.h, p_ov, False, y_ov, r_ov)
+    overlap_solve = {"solver": "CGNR on Dov(mu) y = b", "tol": 1e-7, "k": args.k, "ell": args.ell,
+                     "iterations": it_ov, "recursive_residual": res_ov, "rc": rc_ov,
+                     "true_residual": rel(r_ov, b_ov), "ms": t_ov * 1e3,
+                     "ms_per_iteration": t_ov * 1e3 / max(it_ov, 1),
+                     "sign_applications": 2 * it_ov + 1}
+    del b_ov, y_ov, r_ov
+
     ng = nk.nk_stencil_groups(lat.h, nk.NK_PREC_FP64, False)
     V = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3]
 
@@ -580,6 +600,7 @@ def main() -> int:
         "batching_16x16x16x32": batching,
         "learned_scaling_24x24x24x24": rh24,
         "deflation_m32": deflation,
+        "overlap_solve": overlap_solve,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.k, args.ell, args.cpu_sample_steps)
