@@ -30,8 +30,10 @@
  *
  * Threads: calls on one handle must be serialised.  So must, across all
  * handles, every call that reaches the process-wide workspaces:
- * nk_sign_apply[_device], nk_small_sign, nk_inner_matrix, nk_rh_sign,
- * nk_rh_model_set and the learned-scaling kernels.  nk_rh_tile_force and
+ * nk_sign_apply[_device], nk_sign_apply_deflated_device,
+ * nk_overlap_apply_device, nk_overlap_solve_device (these three apply the
+ * sign), nk_small_sign, nk_inner_matrix, nk_rh_sign, nk_rh_model_set and the
+ * learned-scaling kernels.  nk_rh_tile_force and
  * nk_rh_tile_choice are thread-safe.
  *
  * Errors: every entry point returns 0 (NK_OK) on success, a negative code on
