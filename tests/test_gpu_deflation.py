@@ -200,3 +200,15 @@ def test_full_size_free_field(mu):
     assert rc == 0
     assert rel(y, FF.sign_apply_free(x, M_W, mu)) < 1e-10
     lat.close()
+
+
+def test_python_convenience_wrapper(small):
+    mu, lat, u, x, lam, r, l, exact = small
+    banner(f"nk.sign_apply_deflated mu={mu}")
+    b = nk()
+    y1, _, rc1 = _run(lat, x, lam, r, l, mu=mu, m_w=M_W, k=60, ell=30)
+    y2, info = b.sign_apply_deflated(lat, to_dev(x), lam, to_dev(r.T), to_dev(l.T), mu=mu, m_w=M_W, k=60, ell=30)
+    assert info.rc == rc1 == 0
+    assert np.array_equal(to_host(y2), y1)
+    with pytest.raises(ValueError):
+        b.sign_apply_deflated(lat, to_dev(x), lam[:3], to_dev(r.T), to_dev(l.T), mu=mu, k=60, ell=30)
