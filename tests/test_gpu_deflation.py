@@ -212,3 +212,35 @@ def test_python_convenience_wrapper(small):
     assert np.array_equal(to_host(y2), y1)
     with pytest.raises(ValueError):
         b.sign_apply_deflated(lat, to_dev(x), lam[:3], to_dev(r.T), to_dev(l.T), mu=mu, k=60, ell=30)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_deflation_lowers_k_at_1e8(mu):
+    """What deflation is for: the smallest k (on a grid of 20, l = k/4) whose
+    nested result is within 1e-8 of the exact sign, with and without the 16
+    critical eigenpairs deflated.  The oracle's scan on this lattice gives
+    240 -> 200 at mu = 0 and 300 -> 240 at mu = 0.3."""
+    dims = (2, 4, 4, 4)
+    banner(f"deflation 2x4x4x4 mu={mu}: smallest k at 1e-8, m = 16 against none")
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    a = W.dense_matrix(u, M_W, mu)
+    lam, r, l = DF.critical_eigenpairs(a, 16, mu == 0.0)
+    exact = D.sign_schur(a) @ x.reshape(-1)
+    b = nk()
+    dx = to_dev(x)
+    dy = torch_cuda().empty_like(dx)
+    R, L = to_dev(r.T), to_dev(l.T)
+    err_p, err_d = {}, {}
+    for k in range(160, 341, 20):
+        p = b.nk_sign_params_default(mu=mu, m_w=M_W, k=k, ell=k // 4)
+        b.nk_sign_apply_device(lat.h, p, dx, dy)
+        err_p[k] = rel(to_host(dy), exact)
+        b.nk_sign_apply_deflated_device(lat.h, p, lam, R, L, dx, dy)
+        err_d[k] = rel(to_host(dy), exact)
+    k_p = min(k for k, e in err_p.items() if e < 1e-8)
+    k_d = min(k for k, e in err_d.items() if e < 1e-8)
+    print(f"mu={mu}: k at 1e-8 undeflated {k_p}, deflated {k_d};",
+          " ".join(f"{k}:{err_p[k]:.1e}/{err_d[k]:.1e}" for k in sorted(err_p)), flush=True)
+    assert k_d < k_p
+    lat.close()
