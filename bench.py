@@ -273,6 +273,13 @@ def main() -> int:
             torch.cuda.synchronize()
             times.append(ev[0].elapsed_time(ev[1]))
         nk.nk_sign_apply_device(lat.h, params(20, 5), x, y)
+        # one deflated application (m = 32 seeded unit vectors standing in for
+        # eigenpairs) for the deflation kernels' counters
+        md = 32
+        dv = [latgen.random_sources(DIMS, md, sd).reshape(md, -1) for sd in (6, 7)]
+        rd, ld = (torch.from_numpy(a / np.linalg.norm(a, axis=1, keepdims=True)).to(dev).reshape(-1) for a in dv)
+        lamd = np.array([1.0 if i % 2 == 0 else -1.0 for i in range(md)], dtype=np.complex128)
+        nk.nk_sign_apply_deflated_device(lat.h, params(20, 5), lamd, rd, ld, x, y)
         torch.cuda.synchronize()
         gbs = 2 * n * 16 / (min(times) / 1e3) / 1e9
         print(json.dumps({"probe": "done", "copy_bytes_read": n * 16, "copy_bytes_written": n * 16,
