@@ -335,16 +335,22 @@ int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int3
  * (sgn(A)^dag = sgn(A^dag) and A^dag = gamma5 Dw(-mu)), with the sign
  * computed by nk_sign_apply_device with the parameters p (nested for
  * ell > 0), so the same errors and warnings apply, a zero source included.
- * gamma5 = diag(1, 1, -1, -1) on the spin index.  x and y must not overlap;
- * one temporary of the size of x is kept in the handle.  Synchronises
+ * m > 0 deflates the sign (Sec. 2) with the m eigenpairs (lam, R, L) of A, as
+ * nk_sign_apply_deflated_device takes them; for Dov^dag the library uses the
+ * eigenpairs of A^dag that these give: eigenvalues conj(lam), right
+ * eigenvectors L, left eigenvectors R.  m = 0: lam, R, L may be NULL.
+ * gamma5 = diag(1, 1, -1, -1) on the spin index.  y must not overlap x, R
+ * or L; one temporary of the size of x is kept in the handle.  Synchronises
  * `stream` before returning; info describes the sign application. */
-int nk_overlap_apply_device(nk_lattice* lat, const nk_sign_params* p, int32_t dagger, const void* x, void* y,
-                            nk_sign_info* info, nk_stream_t stream);
+int nk_overlap_apply_device(nk_lattice* lat, const nk_sign_params* p, int32_t dagger, int32_t m, const double* lam,
+                            const void* R, const void* L, const void* x, void* y, nk_sign_info* info,
+                            nk_stream_t stream);
 
 /* Solve Dov(mu) y = b for one canonical device vector b (p->nrhs must be 1)
  * by the conjugate-gradient method on the normal equations
  * Dov^dag Dov y = Dov^dag b (CGNR), from y = 0, with Dov and Dov^dag applied
- * as nk_overlap_apply_device does (two sign applications per iteration).
+ * as nk_overlap_apply_device does (two sign applications per iteration,
+ * deflated with the m eigenpairs (lam, R, L) when m > 0).
  * Stops when the recursively updated residual |b - Dov y| <= tol |b| or after
  * maxit iterations (NK_WARN_NOTCONV, y the last iterate).  The attainable
  * residual is bounded by the sign's own accuracy at (k, ell).  b = 0 gives
@@ -353,8 +359,9 @@ int nk_overlap_apply_device(nk_lattice* lat, const nk_sign_params* p, int32_t da
  * applications or NK_WARN_NOTCONV; tol <= 0, maxit < 1, nrhs != 1 or b and y
  * overlapping are NK_EINVAL.  Workspace (five vectors) is kept in the handle;
  * synchronises `stream` before returning. */
-int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, double tol, int32_t maxit, const void* b,
-                            void* y, int32_t* iters, double* resid, nk_stream_t stream);
+int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, int32_t m, const double* lam, const void* R,
+                            const void* L, double tol, int32_t maxit, const void* b, void* y, int32_t* iters,
+                            double* resid, nk_stream_t stream);
 
 /* Launch shape of the blocked Gauss-Jordan inverse inside Roberts-Higham for
  * matrices of order > 128 (Eq. (4)): panel threads (256, 512 or 1024) x rows

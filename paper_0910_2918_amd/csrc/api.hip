@@ -818,24 +818,46 @@ int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int3
   return worst;
 }
 
-int nk_overlap_apply_device(nk_lattice* lat, const nk_sign_params* p, int32_t dagger, const void* x, void* y,
-                            nk_sign_info* info, nk_stream_t stream) {
+static int ov_defl(const nk_lattice* lat, int32_t m, const double* lam, const void* R, const void* L, const void* y,
+                   size_t ybytes, OvDefl* d) {
+  if (m < 0 || m > NK_DEFL_MAX || (m > 0 && (!lam || !R || !L))) {
+    set_error("invalid deflation arguments: m = %d, lam/R/L must be given for m > 0", m);
+    return NK_EINVAL;
+  }
+  const size_t cb = (size_t)m * 12 * lat->g.V * sizeof(C64);
+  if (m > 0 && (overlaps(y, ybytes, R, cb) || overlaps(y, ybytes, L, cb))) {
+    set_error("the result overlaps R or L");
+    return NK_EINVAL;
+  }
+  d->m = m;
+  d->lam = lam;
+  d->R = R;
+  d->L = L;
+  return NK_OK;
+}
+
+int nk_overlap_apply_device(nk_lattice* lat, const nk_sign_params* p, int32_t dagger, int32_t m, const double* lam,
+                            const void* R, const void* L, const void* x, void* y, nk_sign_info* info,
+                            nk_stream_t stream) {
   if (int e = validate_params(lat, p)) return e;
   const size_t n = (size_t)12 * lat->g.V * p->nrhs;
   if (!x || !y || overlaps(x, n * sizeof(C64), y, n * sizeof(C64)) || (dagger != 0 && dagger != 1)) {
     set_error("invalid overlap arguments (NULL, overlapping x and y, or dagger not 0/1)");
     return NK_EINVAL;
   }
+  OvDefl d;
+  if (int e = ov_defl(lat, m, lam, R, L, y, n * sizeof(C64), &d)) return e;
   if (lat->ovl.ensure(n * sizeof(C64))) return NK_ENOMEM;
   if (info) {
     std::memset(info, 0, sizeof *info);
     info->est = std::numeric_limits<double>::quiet_NaN();
   }
-  return overlap_apply(lat, p, dagger, (const C64*)x, (C64*)y, lat->ovl.as<C64>(), info, (hipStream_t)stream);
+  return overlap_apply(lat, p, dagger, d, (const C64*)x, (C64*)y, lat->ovl.as<C64>(), info, (hipStream_t)stream);
 }
 
-int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, double tol, int32_t maxit, const void* b,
-                            void* y, int32_t* iters, double* resid, nk_stream_t stream) {
+int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, int32_t m, const double* lam, const void* R,
+                            const void* L, double tol, int32_t maxit, const void* b, void* y, int32_t* iters,
+                            double* resid, nk_stream_t stream) {
   if (int e = validate_params(lat, p)) return e;
   const size_t n = (size_t)12 * lat->g.V;
   if (p->nrhs != 1 || !(tol > 0.0) || !std::isfinite(tol) || maxit < 1 || !b || !y || !iters || !resid ||
@@ -843,9 +865,11 @@ int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, double tol
     set_error("invalid overlap-solve arguments (nrhs must be 1, tol > 0, maxit >= 1, b and y apart)");
     return NK_EINVAL;
   }
+  OvDefl d;
+  if (int e = ov_defl(lat, m, lam, R, L, y, n * sizeof(C64), &d)) return e;
   int it = 0;
   double res = 0.0;
-  const int e = overlap_solve(lat, p, tol, maxit, (const C64*)b, (C64*)y, &it, &res, (hipStream_t)stream);
+  const int e = overlap_solve(lat, p, d, tol, maxit, (const C64*)b, (C64*)y, &it, &res, (hipStream_t)stream);
   *iters = it;
   *resid = res;
   return e;

@@ -235,10 +235,17 @@ int defl_partials(size_t n);
 int defl_dots(const C64* a, int m, size_t n, const C64* x, C64* part, C64* c, hipStream_t st);
 // overlap.hip: y = Dov x (dagger = 0) or Dov^dag x, p->nrhs sources, tmp as
 // large as x; CGNR for Dov y = b (one source)
-int overlap_apply(nk_lattice* lat, const nk_sign_params* p, int dagger, const C64* x, C64* y, C64* tmp,
-                  nk_sign_info* info, hipStream_t st);
-int overlap_solve(nk_lattice* lat, const nk_sign_params* p, double tol, int maxit, const C64* b, C64* y,
-                  int* iters, double* resid, hipStream_t st);
+// d.m > 0: the sign applications are deflated with (d.lam, d.R, d.L)
+struct OvDefl {
+  int m = 0;
+  const double* lam = nullptr;
+  const void* R = nullptr;
+  const void* L = nullptr;
+};
+int overlap_apply(nk_lattice* lat, const nk_sign_params* p, int dagger, const OvDefl& d, const C64* x, C64* y,
+                  C64* tmp, nk_sign_info* info, hipStream_t st);
+int overlap_solve(nk_lattice* lat, const nk_sign_params* p, const OvDefl& d, double tol, int maxit, const C64* b,
+                  C64* y, int* iters, double* resid, hipStream_t st);
 // mode 0: out = x - R c; mode 1: out += R sgn(Lambda) c
 int defl_combine(const C64* r, int m, size_t n, const C64* c, const DeflSigns& neg, int mode, const C64* x, C64* out,
                  hipStream_t st);

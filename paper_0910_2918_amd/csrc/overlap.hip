@@ -68,19 +68,29 @@ int worse(int a, int b) { return b > a ? b : a; }
 
 }  // namespace
 
-int overlap_apply(nk_lattice* lat, const nk_sign_params* p, int dagger, const C64* x, C64* y, C64* tmp,
-                  nk_sign_info* info, hipStream_t st) {
+int overlap_apply(nk_lattice* lat, const nk_sign_params* p, int dagger, const OvDefl& d, const C64* x, C64* y,
+                  C64* tmp, nk_sign_info* info, hipStream_t st) {
   const size_t n = (size_t)12 * lat->g.V * p->nrhs;
   int e;
   if (!dagger) {
-    e = nk_sign_apply_device(lat, p, x, tmp, info, st);  // tmp = sgn(A) x
+    // tmp = sgn(A) x, deflated with (lambda, R, L) when given
+    e = d.m > 0 ? nk_sign_apply_deflated_device(lat, p, d.m, d.lam, d.R, d.L, x, tmp, info, st)
+                : nk_sign_apply_device(lat, p, x, tmp, info, st);
     if (e < 0) return e;
     hipLaunchKernelGGL(k_ov_add_g5, grid_of(n), dim3(OT), 0, st, x, tmp, y, n);
   } else {
     hipLaunchKernelGGL(k_ov_g5, grid_of(n), dim3(OT), 0, st, x, tmp, n);  // tmp = gamma5 x
     nk_sign_params q = *p;
     q.mu = -p->mu;  // A^dag = gamma5 Dw(-mu)
-    e = nk_sign_apply_device(lat, &q, tmp, y, info, st);  // y = sgn(A^dag) gamma5 x
+    if (d.m > 0) {
+      // A^dag has the conjugate eigenvalues, right eigenvectors L and left
+      // eigenvectors R (with R^dag L = I), so its deflation swaps the two
+      std::vector<double> lc(d.lam, d.lam + 2 * d.m);
+      for (int i = 0; i < d.m; ++i) lc[2 * i + 1] = -lc[2 * i + 1];
+      e = nk_sign_apply_deflated_device(lat, &q, d.m, lc.data(), d.L, d.R, tmp, y, info, st);
+    } else {
+      e = nk_sign_apply_device(lat, &q, tmp, y, info, st);  // y = sgn(A^dag) gamma5 x
+    }
     if (e < 0) return e;
     hipLaunchKernelGGL(k_ov_add, grid_of(n), dim3(OT), 0, st, x, y, y, n);
   }
@@ -89,8 +99,8 @@ int overlap_apply(nk_lattice* lat, const nk_sign_params* p, int dagger, const C6
   return e;
 }
 
-int overlap_solve(nk_lattice* lat, const nk_sign_params* p, double tol, int maxit, const C64* b, C64* y,
-                  int* iters, double* resid, hipStream_t st) {
+int overlap_solve(nk_lattice* lat, const nk_sign_params* p, const OvDefl& d, double tol, int maxit, const C64* b,
+                  C64* y, int* iters, double* resid, hipStream_t st) {
   const size_t n = (size_t)12 * lat->g.V;
   const int nb = defl_partials(n);
   if (lat->ovl.ensure((5 * n + nb + 2) * sizeof(C64))) return NK_ENOMEM;
@@ -126,7 +136,7 @@ int overlap_solve(nk_lattice* lat, const nk_sign_params* p, double tol, int maxi
   const double nrm_b = std::sqrt(hb);
   int warn = NK_OK;
   NK_HIP(hipMemcpyAsync(r, b, n * sizeof(C64), hipMemcpyDeviceToDevice, st));
-  int e = overlap_apply(lat, p, 1, r, z, tmp, nullptr, st);  // z = Dov^dag r
+  int e = overlap_apply(lat, p, 1, d, r, z, tmp, nullptr, st);  // z = Dov^dag r
   if (e < 0) return e;
   warn = worse(warn, e);
   NK_HIP(hipMemcpyAsync(pd, z, n * sizeof(C64), hipMemcpyDeviceToDevice, st));
@@ -137,7 +147,7 @@ int overlap_solve(nk_lattice* lat, const nk_sign_params* p, double tol, int maxi
   int it = 0;
   while (it < maxit && res > tol) {
     ++it;
-    e = overlap_apply(lat, p, 0, pd, w, tmp, nullptr, st);  // w = Dov p
+    e = overlap_apply(lat, p, 0, d, pd, w, tmp, nullptr, st);  // w = Dov p
     if (e < 0) return e;
     warn = worse(warn, e);
     double ww = 0.0;
@@ -155,7 +165,7 @@ int overlap_solve(nk_lattice* lat, const nk_sign_params* p, double tol, int maxi
     if (int e2 = read(1, &rr)) return e2;
     res = std::sqrt(rr) / nrm_b;
     if (res <= tol || it == maxit) break;
-    e = overlap_apply(lat, p, 1, r, z, tmp, nullptr, st);  // z = Dov^dag r
+    e = overlap_apply(lat, p, 1, d, r, z, tmp, nullptr, st);  // z = Dov^dag r
     if (e < 0) return e;
     warn = worse(warn, e);
     double zn = 0.0;

@@ -182,9 +182,10 @@ def library():
         "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
         "nk_sign_apply_deflated_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, vp, vp,
                                                     P(nk_sign_info), vp]),
-        "nk_overlap_apply_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, P(nk_sign_info), vp]),
-        "nk_overlap_solve_device": (C.c_int, [vp, P(nk_sign_params), C.c_double, i32, vp, vp, P(i32),
-                                              P(C.c_double), vp]),
+        "nk_overlap_apply_device": (C.c_int, [vp, P(nk_sign_params), i32, i32, vp, vp, vp, vp, vp,
+                                              P(nk_sign_info), vp]),
+        "nk_overlap_solve_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, C.c_double, i32, vp, vp,
+                                              P(i32), P(C.c_double), vp]),
         "nk_stencil_groups": (C.c_int, [vp, i32, i32]),
         "nk_rh_tile_force": (C.c_int, [i32, i32, i32]),
         "nk_rh_tile_choice": (C.c_int, [i32, i32, P(i32)]),
@@ -464,20 +465,35 @@ def nk_sign_apply_deflated_device(h, params: nk_sign_params, lam, R, L, x, y, st
     return info, rc
 
 
-def nk_overlap_apply_device(h, params: nk_sign_params, dagger: bool, x, y, stream=None):
-    """y = Dov x or Dov^dag x on device tensors; returns (info, rc)."""
+def _defl_args(lam, R, L):
+    """(m, lam pointer, R, L pointers, keep-alive) for the optional deflation arguments."""
+    if lam is None:
+        return 0, None, None, None, None
+    lam = np.ascontiguousarray(lam, dtype=np.complex128).reshape(-1)
+    return int(lam.size), _hptr(lam), _dptr(R), _dptr(L), lam
+
+
+def nk_overlap_apply_device(h, params: nk_sign_params, dagger: bool, x, y, stream=None, lam=None, R=None, L=None):
+    """y = Dov x or Dov^dag x on device tensors, optionally with the sign
+    deflated by the eigenpairs (lam, R, L) of A; returns (info, rc)."""
+    m, lp, rp, lvp, keep = _defl_args(lam, R, L)
     info = nk_sign_info()
-    rc = _check(library().nk_overlap_apply_device(h, C.byref(params), 1 if dagger else 0, _dptr(x), _dptr(y),
-                                                  C.byref(info), _stream(stream)))
+    rc = _check(library().nk_overlap_apply_device(h, C.byref(params), 1 if dagger else 0, m, lp, rp, lvp, _dptr(x),
+                                                  _dptr(y), C.byref(info), _stream(stream)))
+    del keep
     return info, rc
 
 
-def nk_overlap_solve_device(h, params: nk_sign_params, tol: float, maxit: int, b, y, stream=None):
-    """CGNR for Dov y = b on device tensors; returns (iterations, relative residual, rc)."""
+def nk_overlap_solve_device(h, params: nk_sign_params, tol: float, maxit: int, b, y, stream=None, lam=None, R=None,
+                            L=None):
+    """CGNR for Dov y = b on device tensors, optionally deflated; returns
+    (iterations, relative residual, rc)."""
+    m, lp, rp, lvp, keep = _defl_args(lam, R, L)
     it = C.c_int32(0)
     res = C.c_double(0.0)
-    rc = _check(library().nk_overlap_solve_device(h, C.byref(params), float(tol), int(maxit), _dptr(b), _dptr(y),
-                                                  C.byref(it), C.byref(res), _stream(stream)))
+    rc = _check(library().nk_overlap_solve_device(h, C.byref(params), m, lp, rp, lvp, float(tol), int(maxit),
+                                                  _dptr(b), _dptr(y), C.byref(it), C.byref(res), _stream(stream)))
+    del keep
     return it.value, res.value, rc
 
 

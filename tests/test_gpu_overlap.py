@@ -134,3 +134,34 @@ def test_full_size_solve(big):
     assert rc == 0 and res <= 1e-7 and it < 60
     dr, _ = _apply(lat, to_host(dy).reshape(xs[0].shape), False, **kw)
     assert rel(dr, xs[0]) < 1e-6
+
+
+def test_deflated_overlap_and_solve(small):
+    """Dov and Dov^dag with the sign deflated by 16 critical eigenpairs of A
+    (Dov^dag uses the eigenpairs of A^dag these give: conj(lambda), L, R), at
+    k = 200 where the undeflated operator is still far off; and CGNR with it."""
+    from oracle import deflation as DF
+
+    mu, lat, xs, dov = small
+    banner(f"deflated overlap 2x2x4x4 mu={mu} k=200 m=16")
+    b = nk()
+    u = latgen.random_gauge((2, 2, 4, 4), 0.8, 0)
+    lam, r, l = DF.critical_eigenpairs(W.dense_matrix(u, M_W, mu), 16, mu == 0.0)
+    R, L = to_dev(r.T), to_dev(l.T)
+    p = _params(mu=mu, k=200, ell=0)
+    dx = to_dev(xs[0])
+    dy = torch_cuda().empty_like(dx)
+    for dagger in (False, True):
+        ref = (dov.conj().T if dagger else dov) @ xs[0].reshape(-1)
+        b.nk_overlap_apply_device(lat.h, p, dagger, dx, dy, lam=lam, R=R, L=L)
+        e_d = rel(to_host(dy), ref)
+        b.nk_overlap_apply_device(lat.h, p, dagger, dx, dy)
+        e_p = rel(to_host(dy), ref)
+        assert e_d < 1e-8 and e_p > 100 * e_d, (dagger, e_d, e_p)
+    db = to_dev(xs[1])
+    it, res, rc = b.nk_overlap_solve_device(lat.h, p, 1e-9, 100, db, dy, lam=lam, R=R, L=L)
+    assert rc == 0 and res <= 1e-9
+    assert rel(to_host(dy), np.linalg.solve(dov, xs[1].reshape(-1))) < 1e-8
+    with pytest.raises(b.NKError) as ei:
+        b.nk_overlap_apply_device(lat.h, p, False, dx, R[: dx.numel()], lam=lam, R=R, L=L)
+    assert ei.value.code == b.NK_EINVAL

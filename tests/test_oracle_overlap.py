@@ -86,3 +86,23 @@ def test_cgnr_terminates_on_three_distinct_moduli():
     assert it == 3
     assert hist[2] > 1e-3  # not done before the third step
     assert _rel(y, b / d) < 1e-12
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_adjoint_deflation_swaps_left_and_right(mu):
+    """A^dag has the eigenvalues conj(lambda), right eigenvectors L and left
+    eigenvectors R: deflating every eigenpair of A^dag that way gives its
+    spectral sign, i.e. the sign inside Dov^dag."""
+    from oracle import deflation as F
+
+    dims = (2, 2, 2, 2)
+    u = latgen.random_gauge(dims, 1.0, 3)
+    x = latgen.random_sources(dims, 1, 3)[0]
+    a = W.dense_matrix(u, M_W, mu)
+    ad = W.dense_matrix(u, M_W, -mu)
+    assert np.array_equal(ad, a.conj().T)
+    lam, r, l = F.critical_eigenpairs(a, a.shape[0], mu == 0.0)
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    y, _ = F.deflated_sign_apply(f, fd, x, 8, 0, mu == 0.0, lam.conj(), l, r)
+    assert _rel(y, D.sign_schur(ad) @ x.reshape(-1)) < 1e-11
