@@ -329,6 +329,28 @@ int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int3
                                   const void* R, const void* L, const void* x, void* y, nk_sign_info* info,
                                   nk_stream_t stream);
 
+/* The critical eigenpairs that deflation treats exactly (Sec. 2), for the
+ * Hermitian case mu = 0: the m eigenvalues of H = gamma5 Dw(0) (mass m_w)
+ * smallest in modulus, with orthonormal eigenvectors, to pass to
+ * nk_sign_apply_deflated_device as lam, R and L = R.  The paper takes them
+ * as given; this library computes them by Chebyshev-filtered subspace
+ * iteration on H^2 with a block of p vectors (m <= p <= 128; a few more than
+ * m speed convergence) and filter degree `degree`, starting from the p
+ * canonical device vectors V0 (for example Gaussian; not modified), with
+ * Rayleigh-Ritz on H^2 after each filter pass.
+ *   lam     host, m doubles, ascending in modulus;
+ *   R       device, m canonical vectors, one after another;
+ *   *passes filter passes used, *resid the largest |H r_i - lam_i r_i|.
+ * Stops when *resid <= tol * (|4 + m_w| + 8) (a bound on |H|) or after maxit
+ * passes (NK_WARN_NOTCONV, the current Ritz pairs returned).  The
+ * eigenvalues of H^2 just above the block limit the speed: the smaller the
+ * gap, the more passes.  NK_EINVAL for bad sizes or R overlapping V0, or if
+ * the block loses rank; NK_ENOGAUGE without a gauge field.  Workspace (four
+ * blocks of p vectors) is kept in the handle.  Synchronises `stream`. */
+int nk_eig_hermitian_device(nk_lattice* lat, double m_w, int32_t m, int32_t p, int32_t degree, double tol,
+                            int32_t maxit, const void* V0, double* lam, void* R, int32_t* passes, double* resid,
+                            nk_stream_t stream);
+
 /* The overlap operator (Sec. 1, Eq. (1)) on p->nrhs canonical device vectors:
  *   dagger = 0: y = Dov(mu) x = x + gamma5 sgn(gamma5 Dw(mu)) x;
  *   dagger = 1: y = Dov(mu)^dag x = x + sgn(gamma5 Dw(-mu)) gamma5 x

@@ -293,6 +293,7 @@ nk_lattice::~nk_lattice() {
   bsmall.release();
   defl.release();
   ovl.release();
+  eig.release();
   for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
 }
 
@@ -871,6 +872,34 @@ int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, int32_t m,
   double res = 0.0;
   const int e = overlap_solve(lat, p, d, tol, maxit, (const C64*)b, (C64*)y, &it, &res, (hipStream_t)stream);
   *iters = it;
+  *resid = res;
+  return e;
+}
+
+int nk_eig_hermitian_device(nk_lattice* lat, double m_w, int32_t m, int32_t p, int32_t degree, double tol,
+                            int32_t maxit, const void* V0, double* lam, void* R, int32_t* passes, double* resid,
+                            nk_stream_t stream) {
+  if (!lat) {
+    set_error("NULL lattice handle");
+    return NK_EINVAL;
+  }
+  if (!lat->have_gauge) {
+    set_error("no gauge field set");
+    return NK_ENOGAUGE;
+  }
+  const size_t n = (size_t)12 * lat->g.V;
+  if (m < 1 || p < m || p > 128 || (size_t)p > n || degree < 1 || degree > 1000 || !(tol > 0.0) ||
+      !std::isfinite(tol) || maxit < 1 || !std::isfinite(m_w) || !V0 || !lam || !R || !passes || !resid ||
+      overlaps(V0, (size_t)p * n * sizeof(C64), R, (size_t)m * n * sizeof(C64))) {
+    set_error("invalid eigensolver arguments (1 <= m <= p <= 128, 1 <= degree <= 1000, tol > 0, maxit >= 1, "
+              "V0 and R apart)");
+    return NK_EINVAL;
+  }
+  int it = 0;
+  double res = 0.0;
+  const int e = eig_hermitian(lat, m_w, m, p, degree, tol, maxit, (const C64*)V0, lam, (C64*)R, &it, &res,
+                              (hipStream_t)stream);
+  *passes = it;
   *resid = res;
   return e;
 }

@@ -204,6 +204,7 @@ struct nk_lattice {
   nk::DevBuf bsmall;   // multi-source path: coefficients, partial sums, small problems
   nk::DevBuf defl;     // deflation: partial sums, projections, projected sources
   nk::DevBuf ovl;      // overlap operator and solver: CG vectors, sign temporaries
+  nk::DevBuf eig;      // eigensolver: four blocks of p vectors, partial sums, p x p matrices
   // multi-source path: sweeps captured as HIP graphs, keyed by their launch arguments
   struct Graph {
     std::vector<char> key;
@@ -235,6 +236,10 @@ int defl_partials(size_t n);
 int defl_dots(const C64* a, int m, size_t n, const C64* x, C64* part, C64* c, hipStream_t st);
 // overlap.hip: y = Dov x (dagger = 0) or Dov^dag x, p->nrhs sources, tmp as
 // large as x; CGNR for Dov y = b (one source)
+// eig.hip: the m eigenpairs of gamma5 Dw(0) smallest in modulus (block of p,
+// Chebyshev degree `degree`), starting from the p vectors v0
+int eig_hermitian(nk_lattice* lat, double m_w, int m, int p, int degree, double tol, int maxit, const C64* v0,
+                  double* lam, C64* r_out, int* passes, double* resid, hipStream_t st);
 // d.m > 0: the sign applications are deflated with (d.lam, d.R, d.L)
 struct OvDefl {
   int m = 0;

@@ -73,6 +73,7 @@ EXPORTS = (
     "nk_sign_apply",
     "nk_sign_apply_device",
     "nk_sign_apply_deflated_device",
+    "nk_eig_hermitian_device",
     "nk_overlap_apply_device",
     "nk_overlap_solve_device",
     "nk_stencil_groups",
@@ -182,6 +183,8 @@ def library():
         "nk_sign_apply_device": (C.c_int, [vp, P(nk_sign_params), vp, vp, P(nk_sign_info), vp]),
         "nk_sign_apply_deflated_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, vp, vp,
                                                     P(nk_sign_info), vp]),
+        "nk_eig_hermitian_device": (C.c_int, [vp, C.c_double, i32, i32, i32, C.c_double, i32, vp, vp, vp, P(i32),
+                                              P(C.c_double), vp]),
         "nk_overlap_apply_device": (C.c_int, [vp, P(nk_sign_params), i32, i32, vp, vp, vp, vp, vp,
                                               P(nk_sign_info), vp]),
         "nk_overlap_solve_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, C.c_double, i32, vp, vp,
@@ -463,6 +466,18 @@ def nk_sign_apply_deflated_device(h, params: nk_sign_params, lam, R, L, x, y, st
     rc = _check(library().nk_sign_apply_deflated_device(h, C.byref(params), m, _hptr(lam), _dptr(R), _dptr(L),
                                                         _dptr(x), _dptr(y), C.byref(info), _stream(stream)))
     return info, rc
+
+
+def nk_eig_hermitian_device(h, m_w: float, m: int, p: int, degree: int, tol: float, maxit: int, V0, R, stream=None):
+    """The m eigenpairs of gamma5 Dw(0) smallest in modulus; V0 holds p start
+    vectors, R receives m.  Returns (lam, passes, resid, rc)."""
+    lam = np.zeros(int(m), dtype=np.float64)
+    it = C.c_int32(0)
+    res = C.c_double(0.0)
+    rc = _check(library().nk_eig_hermitian_device(h, float(m_w), int(m), int(p), int(degree), float(tol), int(maxit),
+                                                  _dptr(V0), C.c_void_p(lam.ctypes.data), _dptr(R), C.byref(it),
+                                                  C.byref(res), _stream(stream)))
+    return lam, it.value, res.value, rc
 
 
 def _defl_args(lam, R, L):

@@ -1,0 +1,89 @@
+"""GPU parity of the Hermitian critical-eigenpair solver (deflation, Sec. 2, mu = 0).
+
+* 2x2x4x4: the 16 eigenvalues of gamma5 Dw(0) smallest in modulus against the
+  oracle's dense eigen-decomposition (1e-10), orthonormal eigenvectors, and
+  residuals |H r - lambda r| recomputed with the oracle's stencil;
+* what they are for: deflating a nested sign application on 2x4x4x4 with the
+  GPU's own eigenpairs is as accurate as with the dense ones, and more
+  accurate than no deflation at the same k;
+* invalid arguments.
+"""
+import numpy as np
+import pytest
+
+import latgen
+from oracle import deflation as DF
+from oracle import dense as D
+from oracle import wilson as W
+from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _eig(lat, dims, m, p, degree=20, tol=1e-11, maxit=80, seed=11):
+    b = nk()
+    V0 = to_dev(latgen.random_sources(dims, p, seed))
+    R = torch_cuda().empty(m * V0.numel() // p, dtype=V0.dtype, device=V0.device)
+    lam, passes, resid, rc = b.nk_eig_hermitian_device(lat.h, M_W, m, p, degree, tol, maxit, V0, R)
+    return lam, to_host(R).reshape(m, -1).T, passes, resid, rc
+
+
+def test_matches_dense():
+    dims = (2, 2, 4, 4)
+    banner("eigensolver 2x2x4x4 mu=0 m=16 p=24")
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    lam, r, passes, resid, rc = _eig(lat, dims, 16, 24)
+    print(f"passes {passes} resid {resid:.2e}", flush=True)
+    assert rc == 0 and resid <= 1e-11 * 11.0
+    lam_d, _, _ = DF.critical_eigenpairs(W.dense_matrix(u, M_W, 0.0), 16, True)
+    assert np.max(np.abs(lam - lam_d.real)) < 1e-10
+    assert np.linalg.norm(r.conj().T @ r - np.eye(16)) < 1e-12
+    shape = (4, 4, 2, 2, 4, 3)
+    for i in range(16):
+        hr = W.a_apply(u, r[:, i].reshape(shape), M_W, 0.0).reshape(-1)
+        assert np.linalg.norm(hr - lam[i] * r[:, i]) < 2e-10
+    lat.close()
+
+
+def test_deflation_with_gpu_eigenpairs():
+    dims = (2, 4, 4, 4)
+    banner("eigensolver 2x4x4x4 mu=0: deflation with the GPU's eigenpairs")
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    lam, r, passes, resid, rc = _eig(lat, dims, 16, 24)
+    assert rc == 0
+    a = W.dense_matrix(u, M_W, 0.0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    exact = D.sign_spectral(a, hermitian=True) @ x.reshape(-1)
+    b = nk()
+    p = b.nk_sign_params_default(mu=0.0, m_w=M_W, k=200, ell=50)
+    dx = to_dev(x)
+    dy = torch_cuda().empty_like(dx)
+    R = to_dev(r.T)
+    b.nk_sign_apply_deflated_device(lat.h, p, lam.astype(np.complex128), R, R, dx, dy)
+    e_gpu = rel(to_host(dy), exact)
+    lam_d, r_d, l_d = DF.critical_eigenpairs(a, 16, True)
+    b.nk_sign_apply_deflated_device(lat.h, p, lam_d, to_dev(r_d.T), to_dev(l_d.T), dx, dy)
+    e_dense = rel(to_host(dy), exact)
+    b.nk_sign_apply_device(lat.h, p, dx, dy)
+    e_none = rel(to_host(dy), exact)
+    print(f"k=200: deflated (GPU eigenpairs) {e_gpu:.2e}, (dense) {e_dense:.2e}, none {e_none:.2e}", flush=True)
+    assert e_gpu < 1.5 * e_dense + 1e-12
+    assert e_gpu < e_none / 4
+    lat.close()
+
+
+def test_invalid_arguments():
+    dims = (2, 2, 2, 2)
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    b = nk()
+    V0 = to_dev(latgen.random_sources(dims, 8, 1))
+    R = torch_cuda().empty(4 * 192, dtype=V0.dtype, device=V0.device)
+    for m, p, deg, tol, it in ((0, 8, 10, 1e-8, 5), (9, 8, 10, 1e-8, 5), (4, 8, 0, 1e-8, 5), (4, 8, 10, 0.0, 5),
+                               (4, 8, 10, 1e-8, 0), (4, 129, 10, 1e-8, 5)):
+        with pytest.raises(b.NKError) as ei:
+            b.nk_eig_hermitian_device(lat.h, M_W, m, p, deg, tol, it, V0, R)
+        assert ei.value.code == b.NK_EINVAL
+    with pytest.raises(b.NKError) as ei:
+        b.nk_eig_hermitian_device(lat.h, M_W, 4, 8, 10, 1e-8, 5, V0, V0[: 4 * 192])
+    assert ei.value.code == b.NK_EINVAL
+    lat.close()
