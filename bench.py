@@ -404,6 +404,32 @@ def main() -> int:
                  "overhead_GBps": defl_bytes / max(t_over, 1e-9) / 1e9}
     del rd, ld
 
+    # the Hermitian eigensolver for deflation at mu = 0 on the same lattice:
+    # the 16 eigenpairs of gamma5 Dw(0) smallest in modulus, then the nested
+    # sign at mu = 0 (same k, l) with and without them, against a
+    # non-nested reference at k = 1000
+    m_e, p_e, deg_e = 16, 32, 40
+    V0 = torch.from_numpy(latgen.random_sources(DIMS, p_e, 11).reshape(-1)).to(dev)
+    R_e = torch.empty(m_e * 12 * DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3], dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam_e, passes_e, res_e, rc_e = nk.nk_eig_hermitian_device(lat.h, M_W, m_e, p_e, deg_e, 1e-10, 100, V0, R_e)
+    t_e = time.perf_counter() - t0
+    del V0
+    p0 = nk.nk_sign_params_default(k=1000, ell=0, mu=0.0, m_w=M_W)
+    y0ref = torch.empty_like(x)
+    nk.nk_sign_apply_device(lat.h, p0, x, y0ref)
+    p0 = nk.nk_sign_params_default(k=args.k, ell=args.ell, mu=0.0, m_w=M_W)
+    nk.nk_sign_apply_device(lat.h, p0, x, y)
+    e_none = rel(y, y0ref)
+    nk.nk_sign_apply_deflated_device(lat.h, p0, lam_e.astype(np.complex128), R_e, R_e, x, y)
+    e_defl = rel(y, y0ref)
+    eig_mu0 = {"m": m_e, "block": p_e, "degree": deg_e, "passes": passes_e, "residual": res_e, "rc": rc_e,
+               "s": t_e, "abs_lambda_min": float(np.abs(lam_e).min()), "abs_lambda_max": float(np.abs(lam_e).max()),
+               "nested_mu0_err_undeflated": e_none, "nested_mu0_err_deflated": e_defl,
+               "k": args.k, "ell": args.ell, "reference": "non-nested k=1000, mu=0"}
+    del R_e, y0ref
+
     # the overlap operator of Eq. (1) in a linear solve: CGNR for Dov y = b at
     # the same (k, l), two sign applications per iteration; the true residual
     # is checked with one more application
@@ -608,6 +634,7 @@ def main() -> int:
         "learned_scaling_24x24x24x24": rh24,
         "deflation_m32": deflation,
         "overlap_solve": overlap_solve,
+        "eigensolver_mu0": eig_mu0,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.k, args.ell, args.cpu_sample_steps)

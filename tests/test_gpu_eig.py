@@ -87,3 +87,23 @@ def test_invalid_arguments():
         b.nk_eig_hermitian_device(lat.h, M_W, 4, 8, 10, 1e-8, 5, V0, V0[: 4 * 192])
     assert ei.value.code == b.NK_EINVAL
     lat.close()
+
+
+def test_full_size():
+    """16^4 (the benchmark lattice at mu = 0): converged residuals, checked
+    again with the library's own stencil call, and orthonormal vectors."""
+    dims = (16, 16, 16, 16)
+    banner("eigensolver 16^4 mu=0 m=16 p=32 degree=40")
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    lam, r, passes, resid, rc = _eig(lat, dims, 16, 32, degree=40, tol=1e-10, maxit=100)
+    print(f"passes {passes} resid {resid:.2e} |lam| {np.abs(lam).min():.4f}..{np.abs(lam).max():.4f}", flush=True)
+    assert rc == 0 and resid <= 1.1e-9
+    assert np.all(np.diff(np.abs(lam)) > -1e-9)
+    assert np.linalg.norm(r.conj().T @ r - np.eye(16)) < 1e-11
+    b = nk()
+    for i in (0, 15):
+        dr = to_dev(r[:, i])
+        dh = torch_cuda().empty_like(dr)
+        b.nk_apply_dw_device(lat.h, M_W, 0.0, True, dr, dh)
+        assert np.linalg.norm(to_host(dh) - lam[i] * r[:, i]) < 1.2e-9
+    lat.close()
