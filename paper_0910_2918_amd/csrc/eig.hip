@@ -15,7 +15,11 @@
 //   * it stops when the m leading residuals |H r - lambda r| are below
 //     tol * sqrt(b2).
 // Vector work (stencil, Chebyshev steps, Gram matrices, block combinations)
-// runs in kernels; the p x p Cholesky and Jacobi steps run on the host.
+// runs in kernels; the p x p Cholesky and Jacobi steps run on the host.  The
+// iteration works in the library's packed device layout, one stencil launch
+// per vector: every other step is an inner product or a linear combination,
+// which a fixed reordering of the entries leaves unchanged, so the start
+// block is packed once and the result unpacked once.
 #include <algorithm>
 #include <cmath>
 #include <utility>
@@ -124,7 +128,11 @@ int eig_hermitian(nk_lattice* lat, double m_w, int m, int p, int degree, double 
   C64* T = bufs[3];   // H Y inside the filter, orthonormalisation scratch
   const double hb = std::fabs(4.0 + m_w) + 8.0, b2 = hb * hb;
   const dim3 grid((unsigned)((blk + ET - 1) / ET));
-  auto applyH = [&](const C64* x, C64* y) { return nk_apply_dw_device(lat, m_w, 0.0, 1, x, y, p, st); };
+  auto applyH = [&](const C64* x, C64* y) -> int {
+    for (int i = 0; i < p; ++i)
+      if (int e = nk_apply_dw_packed_device(lat, m_w, 0.0, 1, x + (size_t)i * n, y + (size_t)i * n, st)) return e;
+    return NK_OK;
+  };
 
   std::vector<double> t2, th(p), res(p);
   // Rayleigh-Ritz with H^2 on the orthonormal V; leaves V rotated, Wb = H V,
@@ -168,7 +176,7 @@ int eig_hermitian(nk_lattice* lat, double m_w, int m, int p, int degree, double 
     return NK_OK;
   };
 
-  NK_HIP(hipMemcpyAsync(V, v0, blk * sizeof(C64), hipMemcpyDeviceToDevice, st));
+  if (int e = nk_spinor_pack_device(lat, v0, V, p, st)) return e;
   if (int e = orthonormalise(w, V, T)) return e;
   if (int e = rayleigh_ritz()) return e;
   int it = 0;
@@ -200,7 +208,7 @@ int eig_hermitian(nk_lattice* lat, double m_w, int m, int p, int degree, double 
     if (int er = rayleigh_ritz()) return er;
     worst = *std::max_element(res.begin(), res.begin() + m);
   }
-  NK_HIP(hipMemcpyAsync(r_out, V, (size_t)m * n * sizeof(C64), hipMemcpyDeviceToDevice, st));
+  if (int e = nk_spinor_unpack_device(lat, V, r_out, m, st)) return e;
   NK_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < m; ++i) lam[i] = th[i];
   *passes = it;
