@@ -226,7 +226,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the library has no multi-GPU path",
                           "n_gpus": args.gpus}))
         return 2
 
