@@ -244,3 +244,23 @@ def test_deflation_lowers_k_at_1e8(mu):
           " ".join(f"{k}:{err_p[k]:.1e}/{err_d[k]:.1e}" for k in sorted(err_p)), flush=True)
     assert k_d < k_p
     lat.close()
+
+
+def test_graph_replays_and_reduced_precision(small):
+    """The deflated path under the other execution modes it passes through:
+    lockstep sweeps replayed from captured graphs (block = 2) agree with one
+    source at a time, and FP32 spinors and links stay within the reduced
+    precision's error of the FP64 deflated result."""
+    mu, lat, u, x, lam, r, l, exact = small
+    banner(f"deflation with graph replays and FP32, mu={mu}")
+    xs = latgen.random_sources(x.shape[:4][::-1], 3, 9)
+    yb, _, rcb = _run(lat, xs, lam, r, l, nrhs=3, mu=mu, k=60, ell=30, block=2)
+    yb2, _, _ = _run(lat, xs, lam, r, l, nrhs=3, mu=mu, k=60, ell=30, block=2)  # replays the captured graphs
+    yb, yb2 = yb.reshape(3, -1), yb2.reshape(3, -1)
+    assert np.array_equal(yb, yb2)
+    for s in range(3):
+        ys, _, _ = _run(lat, xs[s], lam, r, l, mu=mu, k=60, ell=30)
+        assert rel(yb[s], ys) < 1e-9
+    y64, _, _ = _run(lat, x, lam, r, l, mu=mu, k=80, ell=40)
+    y32, _, _ = _run(lat, x, lam, r, l, mu=mu, k=80, ell=40, precision=1)
+    assert rel(y32, y64) < 1e-5
