@@ -61,15 +61,22 @@ struct EigWork {
   hipStream_t st;
 };
 
-// h[i + j * pa] = a_i^dag b_j
-int gram(const EigWork& w, const C64* a, int pa, const C64* b, int pb, std::vector<cd>& h) {
-  for (int j = 0; j < pb; ++j)
-    if (int e = defl_dots(a, pa, w.n, b + (size_t)j * w.n, w.part, w.dg + (size_t)j * pa, w.st)) return e;
-  std::vector<C64> t((size_t)pa * pb);
+// h[i + j * p] = a_i^dag a_j for the p columns of a: the upper triangle on the
+// device (column j against columns 0 .. j), the lower one by Hermitian symmetry
+int gram(const EigWork& w, const C64* a, std::vector<cd>& h) {
+  const int p = w.p;
+  for (int j = 0; j < p; ++j)
+    if (int e = defl_dots(a, j + 1, w.n, a + (size_t)j * w.n, w.part, w.dg + (size_t)j * p, w.st)) return e;
+  std::vector<C64> t((size_t)p * p);
   NK_HIP(hipMemcpyAsync(t.data(), w.dg, t.size() * sizeof(C64), hipMemcpyDeviceToHost, w.st));
   NK_HIP(hipStreamSynchronize(w.st));
-  h.resize(t.size());
-  for (size_t i = 0; i < t.size(); ++i) h[i] = cd(t[i].re, t[i].im);
+  h.assign(t.size(), cd(0.0, 0.0));
+  for (int j = 0; j < p; ++j)
+    for (int i = 0; i <= j; ++i) {
+      const cd v(t[i + (size_t)j * p].re, t[i + (size_t)j * p].im);
+      h[i + (size_t)j * p] = i == j ? cd(v.real(), 0.0) : v;
+      h[j + (size_t)i * p] = i == j ? cd(v.real(), 0.0) : std::conj(v);
+    }
   return NK_OK;
 }
 
@@ -92,7 +99,7 @@ int orthonormalise(const EigWork& w, C64* y, C64* tmp) {
   for (int pass = 0; pass < 2; ++pass) {
     C64* src = pass == 0 ? y : tmp;
     C64* dst = pass == 0 ? tmp : y;
-    if (int e = gram(w, src, w.p, src, w.p, g)) return e;
+    if (int e = gram(w, src, g)) return e;
     if (!dense::chol_inv_upper(g, w.p)) {
       set_error("eigensolver: the block lost rank (Gram matrix not positive definite)");
       return NK_EINVAL;
@@ -140,13 +147,7 @@ int eig_hermitian(nk_lattice* lat, double m_w, int m, int p, int degree, double 
   auto rayleigh_ritz = [&]() -> int {
     if (int e = applyH(V, Wb)) return e;
     std::vector<cd> g, q;
-    if (int e = gram(w, Wb, p, Wb, p, g)) return e;  // V^dag H^2 V
-    for (int j = 0; j < p; ++j)
-      for (int i = 0; i < j; ++i) {  // exact Hermitian symmetry
-        const cd s = 0.5 * (g[i + (size_t)j * p] + std::conj(g[j + (size_t)i * p]));
-        g[i + (size_t)j * p] = s;
-        g[j + (size_t)i * p] = std::conj(s);
-      }
+    if (int e = gram(w, Wb, g)) return e;  // V^dag H^2 V = (H V)^dag (H V), exactly Hermitian by construction
     dense::jacobi_herm(g, p, t2, q);
     if (int e = combine(w, V, q, p, T)) return e;
     std::swap(V, T);
