@@ -231,8 +231,14 @@ static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64
                           p->rh_maxit, p->rh_tol, cb.z, &so, st, p->inner);
   if (es < 0) return es;
   if (es > 0 && warn == NK_OK) warn = es;
-  if (p->est_delay > 0 && std::isnan(est) && kused - p->est_delay >= 1) {
-    if (int e = estimate(kused, ell, herm, p->est_delay, p, cb, st, &est)) return e;
+  // the estimate at the final k: requested explicitly (est_delay > 0), or
+  // needed for the early-stop verdict when the loop ran to k without its last
+  // check (the in-loop checks skip j1 == k); the delay is the loop's
+  if (std::isnan(est) && (p->est_delay > 0 || p->tol > 0.0)) {
+    const int d = std::max(1, std::min(p->est_delay > 0 ? p->est_delay : 10, kused - 1));
+    if (kused - d >= 1) {
+      if (int e = estimate(kused, ell, herm, d, p, cb, st, &est)) return e;
+    }
   }
   NK_HIP(hipEventRecord(ev[2], st));
   if (two) {

@@ -49,3 +49,21 @@ def rel(a, b) -> float:
 
 def banner(msg: str) -> None:
     print(f"[gpu-case] {msg}", flush=True)
+
+
+def perturbed(x: np.ndarray, seed: int = 99, size: float = 1e-15) -> np.ndarray:
+    """x with every entry changed by a relative amount of about `size`
+    (complex Gaussian, seeded): a change at the level of FP64 rounding."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape)
+    return x * (1.0 + size * d)
+
+
+def method_bound(sens: float) -> float:
+    """Method-level tolerance of GPU against oracle at the same (k, l): the
+    oracle's own result moves by `sens` when its source changes at the
+    rounding level (perturbed), and the GPU, whose reductions round
+    differently at every step of the recurrence, may differ by up to 10
+    times that (measured: at most 3 times, over every method-level case),
+    and by no more than 1e-12 where the recurrence amplifies nothing."""
+    return max(1e-12, 10.0 * sens)

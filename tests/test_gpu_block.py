@@ -1,7 +1,8 @@
 """Many sources in lockstep (nk_sign_params.block = 1), through the C ABI.
 
 Against the oracle's nested / non-nested run of each source at the same
-(k, ell) (method level, <= max(1e-10, 10 eps_true(k))), against the
+(k, ell) (method level, within method_bound of the oracle's own rounding
+sensitivity), against the
 one-at-a-time path, and across the one-pass and two-pass lifts.
 """
 import numpy as np
@@ -10,7 +11,7 @@ import pytest
 import latgen
 from oracle import nested as N
 from oracle import wilson as W
-from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
+from tests.gpu_helpers import M_W, banner, make_lattice, method_bound, nk, perturbed, rel, to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -46,9 +47,9 @@ def test_block_matches_oracle(setup, ells):
     fd = lambda v: W.a_apply(u, v.reshape(xs[0].shape), M_W, -MU).reshape(-1)
     for s in range(4):
         yo, _ = N.sign_apply(f, fd, xs[s], k, ells[s], False)
-        yref, _ = N.sign_apply(f, fd, xs[s], 500, 0, False)
-        eps_true = rel(yo, yref)
-        assert rel(y[s], yo) <= max(1e-10, 10 * eps_true), (s, rel(y[s], yo), eps_true)
+        sens = rel(N.sign_apply(f, fd, perturbed(xs[s]), k, ells[s], False)[0], yo)
+        print(f"[gap] block s={s}: GPU vs oracle {rel(y[s], yo):.3e}, sensitivity {sens:.3e}", flush=True)
+        assert rel(y[s], yo) <= method_bound(sens), (s, rel(y[s], yo), sens)
 
 
 def test_block_matches_one_at_a_time(setup):
@@ -106,7 +107,7 @@ def test_block_mu0_runs_one_at_a_time(setup):
 
 def test_block_8x4_sixteen_sources_uneven_ell():
     """16 sources with uneven ell at 8^4 mu = 0.3 against the one-at-a-time
-    path, at the method level (the truth: non-nested k = 600)."""
+    path, within method_bound of that path's own rounding sensitivity."""
     dims = (8, 8, 8, 8)
     lat, u = make_lattice(dims, 0.6, seed=2)
     xs = latgen.random_sources(dims, 16, 9)
@@ -115,10 +116,14 @@ def test_block_8x4_sixteen_sources_uneven_ell():
     yb, _, rc = _run(lat, xs, k=300, ell_per_rhs=ells, block=1)
     assert rc == 0
     ys, _, _ = _run(lat, xs, k=300, ell_per_rhs=ells, block=0)
-    yt, _, _ = _run(lat, xs, k=600, ell=0, block=1)
+    # rounding sensitivity of the one-at-a-time path itself: the same sources
+    # changed at the rounding level (the oracle would take minutes here)
+    yp, _, _ = _run(lat, np.stack([perturbed(xs[s], seed=100 + s) for s in range(16)]), k=300,
+                    ell_per_rhs=ells, block=0)
     for s in range(16):
-        eps_true = rel(ys[s], yt[s])
-        assert rel(yb[s], ys[s]) <= max(1e-10, 10 * eps_true), (s, rel(yb[s], ys[s]), eps_true)
+        sens = rel(yp[s], ys[s])
+        print(f"[gap] block-vs-single s={s}: {rel(yb[s], ys[s]):.3e}, sensitivity {sens:.3e}", flush=True)
+        assert rel(yb[s], ys[s]) <= method_bound(sens), (s, rel(yb[s], ys[s]), sens)
     lat.close()
 
 

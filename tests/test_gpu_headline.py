@@ -1,0 +1,143 @@
+"""The benchmarked workload against the FP64 oracle, reduced precision against
+the oracle, and the learned scaling's fallback.
+
+* The benchmark's own configuration (16^4, mu = 0.3, m_w = -1, link width 0.8,
+  gauge seed 0, source seed 0, nested with learned Roberts-Higham scaling,
+  one source, stored basis) at a k the oracle finishes in about a minute
+  (k = 120, l = 30), compared with oracle.nested.sign_apply at the same
+  (k, l) (Sec. 2-3, Eqs. (3)-(6)).  The limit of the scaled iteration is the
+  unscaled one (sgn(mu S) = sgn(S) for mu > 0), so the oracle runs the
+  paper's unscaled Roberts-Higham.
+* FP32 and BF16-link results at 4^4 and 8^4 against the FP64 oracle at the
+  same (k, l): the error each precision costs, stated per case.
+* A model whose prediction is NaN, or implausibly large, leaves the learned
+  path exactly on determinant scaling, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import latgen
+from oracle import nested as N
+from oracle import wilson as W
+from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _sign(lat, x, **kw):
+    b = nk()
+    p = b.nk_sign_params_default(**kw)
+    dx = to_dev(x)
+    dy = torch_cuda().empty_like(dx)
+    info, rc = b.nk_sign_apply_device(lat.h, p, dx, dy)
+    return to_host(dy), info, rc
+
+
+def _oracle(u, x, mu, k, ell):
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    return N.sign_apply(f, fd, x, k, ell, mu == 0.0)
+
+
+def _shipped_model():
+    from paper_0910_2918_amd import rh_train
+
+    return np.load(rh_train.WEIGHTS).astype(np.float32)
+
+
+@pytest.mark.timeout(900)
+def test_benchmark_workload_matches_oracle():
+    """16^4, mu = 0.3, eps = 0.8, seed 0, learned scaling, k = 120, l = 30:
+    GPU against the oracle's two-sided Lanczos and nested small problem at the
+    same (k, l).  Both run the same recurrence in FP64; at k = 120 on a space
+    of dimension 786432 the two-sided basis is still close to biorthogonal, so
+    the two results differ by rounding only: 1e-10."""
+    b = nk()
+    dims, mu, k, ell = (16, 16, 16, 16), 0.3, 120, 30
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    b.nk_rh_model_set(_shipped_model())
+    try:
+        banner(f"16^4 mu={mu} eps=0.8 k={k} l={ell} learned scaling, GPU")
+        y, info, rc = _sign(lat, x, k=k, ell=ell, mu=mu, rh_scaling=b.NK_RH_LEARNED)
+        assert rc == 0 and info.k_used == k and info.ell_used == ell
+        banner(f"16^4 mu={mu} k={k} l={ell}: oracle (about a minute of host time)")
+        yo, io = _oracle(u, x, mu, k, ell)
+        gap = rel(y, yo)
+        print(f"[gap] 16^4 mu={mu} k={k} l={ell} learned: GPU vs oracle {gap:.3e} "
+              f"(GPU rh_iters {info.rh_iters}, oracle unscaled {io['rh_iters']})", flush=True)
+        assert gap < 1e-10
+    finally:
+        b.nk_rh_model_set(None)
+        lat.close()
+
+
+@pytest.mark.parametrize("dims,mu,eps,k,ell", [
+    ((4, 4, 4, 4), 0.0, 0.4, 150, 60),
+    ((4, 4, 4, 4), 0.3, 0.4, 150, 60),
+    ((8, 8, 8, 8), 0.3, 0.6, 200, 50),
+])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_reduced_precision_against_oracle(dims, mu, eps, k, ell, prec):
+    """FP32 spinors and links (prec 1) and BF16-stored links (prec 2), with FP64
+    coefficients and small problem, against the FP64 oracle at the same
+    (k, l).  Bounds: FP32 rounds at 6e-8 per operation, and the two-sided
+    recurrence amplifies rounding: the FP64 GPU run of the 8^4 case differs
+    from the oracle by 3e-13, 3000 times FP64 rounding, so FP32 may reach
+    2e-4 there; the bound is 1e-3.  BF16 links carry 2^-9 relative error per
+    entry (rebuilt to SU(3)), a change of the operator itself: 1e-2.  Each
+    error is printed beside the FP64 run's gap to the oracle."""
+    b = nk()
+    lat, u = make_lattice(dims, eps, seed=0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    banner(f"{dims} mu={mu} k={k} l={ell} precision={prec} vs FP64 oracle")
+    y, info, rc = _sign(lat, x, k=k, ell=ell, mu=mu, precision=prec)
+    y64, _, _ = _sign(lat, x, k=k, ell=ell, mu=mu)
+    yo, _ = _oracle(u, x, mu, k, ell)
+    err, gap64 = rel(y, yo), rel(y64, yo)
+    print(f"[precision] {dims} mu={mu} k={k} l={ell} precision {prec}: vs FP64 oracle {err:.3e} "
+          f"(FP64 GPU vs oracle {gap64:.3e})", flush=True)
+    assert rc == 0
+    assert err < (1e-3 if prec == 1 else 1e-2)
+    lat.close()
+
+
+@pytest.mark.parametrize("bad", ["nan", "large"])
+def test_learned_fallback_is_determinant_scaling(bad):
+    """A model that predicts NaN (output bias NaN) or |y| > 30 (output bias 50)
+    must leave every step on determinant scaling: nk_rh_sign and a whole sign
+    application with NK_RH_LEARNED equal NK_RH_DET bit for bit."""
+    b = nk()
+    P = _shipped_model().copy()
+    H, NI, T = b.NK_MLP_HIDDEN, b.NK_MLP_IN, b.NK_MLP_STEPS
+    o_w4 = H * NI + H + 2 * (H * H + H)
+    o_b4 = o_w4 + T * H
+    if bad == "nan":
+        P[o_b4:o_b4 + T] = np.nan
+    else:
+        P[o_w4:o_w4 + T * H] = 0.0
+        P[o_b4:o_b4 + T] = 50.0
+    rng = np.random.default_rng(3)
+    n = np.array([40, 150, 97])
+    ld = 150
+    S = np.zeros((3, ld, ld), np.complex128)
+    for i, m in enumerate(n):
+        a = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+        S[i, :m, :m] = a / np.sqrt(m) + 2.0 * np.diag(np.sign(rng.standard_normal(m)))
+    dims = (4, 4, 4, 4)
+    lat, u = make_lattice(dims, 0.4, seed=0)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    try:
+        b.nk_rh_model_set(P)
+        banner(f"learned fallback ({bad}): nk_rh_sign and a sign application")
+        sl, il, _ = b.nk_rh_sign(S, n, scaling=b.NK_RH_LEARNED)
+        sd, idt, _ = b.nk_rh_sign(S, n, scaling=b.NK_RH_DET)
+        assert np.array_equal(il, idt)
+        assert np.array_equal(sl.view(np.uint64), sd.view(np.uint64))
+        yl, infl, rcl = _sign(lat, x, k=150, ell=60, mu=0.3, rh_scaling=b.NK_RH_LEARNED)
+        yd, infd, rcd = _sign(lat, x, k=150, ell=60, mu=0.3, rh_scaling=b.NK_RH_DET)
+        assert rcl == rcd == 0 and infl.rh_iters == infd.rh_iters
+        assert np.array_equal(yl.view(np.uint64), yd.view(np.uint64))
+    finally:
+        b.nk_rh_model_set(None)
+        lat.close()
