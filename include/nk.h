@@ -407,6 +407,23 @@ int nk_rh_tile_choice(int32_t n, int32_t batch, int32_t shape[4]);
  * per handle on the first outer-basis run and keeps the faster. */
 int nk_stencil_groups(nk_lattice* lat, int32_t precision, int32_t hermitian);
 
+/* Largest lattice (sites) that nk_apply_dw_noalloc_device takes: 16^4. */
+#define NK_NOALLOC_MAX_SITES 65536
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = [gamma5] Dw(mu) x as nk_apply_dw_device, bit for bit, on nrhs canonical
+ * device vectors, asynchronous on `stream`, with the two layout temporaries
+ * (the packed source and the packed result) in a fixed device array of
+ * 2 x 12 x NK_NOALLOC_MAX_SITES complex128 (24 MiB) that each device holds
+ * from its first use until the process ends.  The call allocates and frees
+ * nothing.  Lattices of more than NK_NOALLOC_MAX_SITES sites are NK_EINVAL;
+ * other errors as nk_apply_dw_device.  Every call on one device shares that
+ * device's array, so calls that overlap on one device (on different streams,
+ * or from different threads) race and must be serialised by the caller. */
+int nk_apply_dw_noalloc_device(nk_lattice* lat, double m_w, double mu, int32_t gamma5, const void* x, void* y,
+                               int32_t nrhs, nk_stream_t stream);
+
 /* Thread-local message for the last failure ("" if none). */
 const char* nk_last_error(void);
 

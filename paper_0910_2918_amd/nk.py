@@ -39,6 +39,7 @@ NK_MLP_NTRAIN = 9668
 NK_MLP_NPARAMS = 9700
 
 NK_DEFL_MAX = 1024
+NK_NOALLOC_MAX_SITES = 65536
 
 NK_INNER_SAME = 0
 NK_INNER_ARNOLDI = 1
@@ -79,6 +80,7 @@ EXPORTS = (
     "nk_stencil_groups",
     "nk_rh_tile_force",
     "nk_rh_tile_choice",
+    "nk_apply_dw_noalloc_device",
     "nk_last_error",
     "nk_version",
 )
@@ -164,6 +166,7 @@ def library():
         "nk_gauge_set_device": (C.c_int, [vp, vp, vp]),
         "nk_apply_dw": (C.c_int, [vp, dbl, dbl, i32, vp, vp, i32]),
         "nk_apply_dw_device": (C.c_int, [vp, dbl, dbl, i32, vp, vp, i32, vp]),
+        "nk_apply_dw_noalloc_device": (C.c_int, [vp, dbl, dbl, i32, vp, vp, i32, vp]),
         "nk_apply_pair_device": (C.c_int, [vp, dbl, dbl, vp, vp, vp, vp, vp]),
         "nk_spinor_pack_device": (C.c_int, [vp, vp, vp, i32, vp]),
         "nk_spinor_unpack_device": (C.c_int, [vp, vp, vp, i32, vp]),
@@ -302,6 +305,12 @@ def nk_apply_dw(h, m_w: float, mu: float, gamma5: bool, x: np.ndarray, nrhs: int
 
 def nk_apply_dw_device(h, m_w: float, mu: float, gamma5: bool, x, y, nrhs: int = 1, stream=None) -> None:
     _check(library().nk_apply_dw_device(h, m_w, mu, 1 if gamma5 else 0, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+
+
+def nk_apply_dw_noalloc_device(h, m_w: float, mu: float, gamma5: bool, x, y, nrhs: int = 1, stream=None) -> None:
+    """nk_apply_dw_device with its temporaries in the library's fixed device array (no allocation)."""
+    _check(library().nk_apply_dw_noalloc_device(h, m_w, mu, 1 if gamma5 else 0, _dptr(x), _dptr(y), nrhs,
+                                                _stream(stream)))
 
 
 def nk_apply_pair_device(h, m_w: float, mu: float, v, w, av, adw, stream=None) -> None:
