@@ -75,6 +75,37 @@ def copy_rate(torch, dev) -> float:
     return 2 * n * 16 / (best / 1e3) / 1e9
 
 
+def stream_ceiling(torch, nk, dev, nbytes=1024 ** 3):
+    """What this library's own streaming kernels reach (nk_stream_device):
+    read-only, copy and triad over arrays of nbytes each (1 GiB, four times
+    the Infinity Cache, so every pass streams from HBM), 16 bytes per lane,
+    the best over a sweep of grid sizes, timed with HIP events on the launch
+    stream.  Bytes: read-only n, copy 2 n, triad 3 n."""
+    n = nbytes // 16
+    a = torch.ones(n, dtype=torch.complex128, device=dev)
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {"bytes_per_array": nbytes}
+    for kind, name, mult in ((0, "read_only", 1), (1, "copy", 2), (2, "triad", 3)):
+        best = (float("inf"), 0)
+        for blocks in (1024, 2048, 4096, 8192, 16384):
+            nk.nk_stream_device(kind, a, b if kind == 2 else None, c, blocks)
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(5):
+                nk.nk_stream_device(kind, a, b if kind == 2 else None, c, blocks)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms = ev[0].elapsed_time(ev[1]) / 5
+            if ms < best[0]:
+                best = (ms, blocks)
+        gbs = mult * nbytes / (best[0] / 1e3) / 1e9
+        out[name] = {"GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "ms": best[0], "blocks": best[1]}
+    del a, b, c
+    return out
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("krylov.hip", "stencil.h", "nk_internal.h"):
@@ -450,6 +481,32 @@ def main() -> int:
                      "sign_applications": 2 * it_ov + 1}
     del b_ov, y_ov, r_ov
 
+    # the non-nested small problem alone (Roberts-Higham on the dense k x k
+    # Ritz matrix, Eq. (4)) at k = 500 and 1000, on H_k of this lattice:
+    # the inversion-only iteration and the default with the Newton-Schulz
+    # tail; every step is counted as 8 k^3 real flops, the k^3 complex
+    # multiply-adds of a Gauss-Jordan inverse (a Newton-Schulz step's two
+    # complex products are twice that, so the figure is a lower bound there),
+    # against the 78.6 TFLOP/s FP64 peak
+    rh_dense = {"lattice": "16^4", "mu": MU, "flops_per_step": "8 k^3", "peak_TFLOPs": 78.6}
+    al_d, be_d, de_d, _, _ = nk.nk_krylov_basis_device(lat.h, nk.nk_sign_params_default(k=1000, mu=MU, m_w=M_W), x)
+    for kd in (500, 1000):
+        for ns_on in (False, True):
+            nk.nk_rh_newton_schulz(ns_on)
+            pd_ = nk.nk_sign_params_default()
+            ts_ = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                _, inf_d, _ = nk.nk_small_sign(kd, 0, False, al_d[:kd], be_d[:kd], de_d[:kd], pd_)
+                ts_.append(time.perf_counter() - t0)
+            tbest = min(ts_[1:])
+            tf = inf_d.rh_iters * 8.0 * kd ** 3 / tbest / 1e12
+            rh_dense[f"k{kd}_{'newton_schulz_tail' if ns_on else 'inversions_only'}"] = {
+                "ms": tbest * 1e3, "steps": inf_d.rh_iters, "TFLOPs": tf, "frac_of_fp64_peak": tf / 78.6,
+                "residual": inf_d.rh_residual}
+    nk.nk_rh_newton_schulz(True)
+    del al_d, be_d, de_d
+
     ng = nk.nk_stencil_groups(lat.h, nk.NK_PREC_FP64, False)
     V = DIMS[0] * DIMS[1] * DIMS[2] * DIMS[3]
 
@@ -457,6 +514,7 @@ def main() -> int:
     # HIP events on every launch of a short plain run (k = 60) on the same
     # lattice, after one untimed run (which also tunes the kernel)
     copy_gbs = copy_rate(torch, dev)
+    streams = stream_ceiling(torch, nk, dev)
     step_kernels = {}
     for prec, pname in ((nk.NK_PREC_FP64, "fp64"), (nk.NK_PREC_FP32, "fp32"),
                         (nk.NK_PREC_FP32_BF16LINKS, "fp32_bf16links")):
@@ -626,12 +684,14 @@ def main() -> int:
         },
         "update_kernel": {"avg_launch_us": (t_up / max(n_up, 1)) * 1e3, "launches": int(n_up)},
         "copy_GBps": copy_gbs,
+        "stream_ceiling": streams,
         "step_kernels": step_kernels,
         "stencil": stencil,
         "precision_vs_fp64": precision,
         "block_stencil": block_stencil,
         "batching_16x16x16x32": batching,
         "learned_scaling_24x24x24x24": rh24,
+        "rh_dense": rh_dense,
         "deflation_m32": deflation,
         "overlap_solve": overlap_solve,
         "eigensolver_mu0": eig_mu0,

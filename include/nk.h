@@ -398,6 +398,17 @@ int nk_overlap_solve_device(nk_lattice* lat, const nk_sign_params* p, int32_t m,
  * writes zeros and returns 0 before the autotuner has chosen; NK_EINVAL for
  * n < 1, batch < 1 or a NULL shape.  Both are process-wide and thread-safe. */
 int nk_rh_tile_force(int32_t rows_per_thread, int32_t panel_threads, int32_t update_tile);
+
+/* The Newton-Schulz tail of the Roberts-Higham iteration for orders > 128
+ * (an option of this library, not part of Eq. (4)): once an iterate S
+ * satisfies |I - S^2|_F < 1/2, the remaining steps are S <- S (3 I - S^2) / 2
+ * (two matrix products on the FP64 matrix cores instead of an inversion),
+ * which converges quadratically to the same limit sgn(S_0); the stopping
+ * test is the same.  Tried for a matrix once its relative change per step has
+ * fallen below 0.05.  Process-wide; enable != 0 turns it on (the default),
+ * 0 off (every step an inversion, as Eq. (4)).  Returns the previous
+ * setting.  Thread-safe. */
+int nk_rh_newton_schulz(int32_t enable);
 int nk_rh_tile_choice(int32_t n, int32_t batch, int32_t shape[4]);
 
 /* Direction groups (2 or 4) of the outer-recurrence stencil kernel that the
@@ -406,6 +417,19 @@ int nk_rh_tile_choice(int32_t n, int32_t batch, int32_t shape[4]);
  * NULL handle or an unknown precision.  The autotuner times both kernels once
  * per handle on the first outer-basis run and keeps the faster. */
 int nk_stencil_groups(nk_lattice* lat, int32_t precision, int32_t hermitian);
+
+/* A measurement helper, not part of the method: the bandwidth this
+ * library's own streaming code reaches, the ceiling against which the
+ * stencil and the recurrences are read.  Over n complex128 entries, 16 bytes
+ * per lane per access with four accesses in flight per lane, `blocks`
+ * workgroups of 256 threads (grid-stride):
+ *   kind 0: read a once, c[0 .. blocks) = per-workgroup partial sums of |a_i|^2;
+ *   kind 1: c = a (copy);
+ *   kind 2: c = a + b / 2 (triad).
+ * Device pointers, asynchronous on `stream`; b is read by kind 2 only.
+ * NK_EINVAL for an unknown kind, n < 1, blocks < 1 or a missing pointer. */
+int nk_stream_device(int32_t kind, int64_t n, const void* a, const void* b, void* c, int32_t blocks,
+                     nk_stream_t stream);
 
 /* Largest lattice (sites) that nk_apply_dw_noalloc_device takes: 16^4. */
 #define NK_NOALLOC_MAX_SITES 65536

@@ -602,6 +602,8 @@ int nk_stencil_groups(nk_lattice* lat, int32_t precision, int32_t hermitian) {
 
 int nk_rh_model_set(const float* params) { return nk::mlp_model_set(params); }
 
+int nk_rh_newton_schulz(int32_t enable) { return nk::rh_newton_schulz(enable); }
+
 int nk_rh_tile_force(int32_t rows_per_thread, int32_t panel_threads, int32_t update_tile) {
   return nk::rh_tile_force(rows_per_thread, panel_threads, update_tile);
 }

@@ -330,6 +330,8 @@ int small_inner_batch(int r, const int* k, const int* ell, int hermitian, const 
 // zero: back to the autotuner), or read the autotuner's choice for a size and
 // batch class (returns 0 before it has chosen)
 int rh_tile_force(int rm, int pth, int tile);
+// the Newton-Schulz tail of the large path on (1) or off (0); returns the previous setting
+int rh_newton_schulz(int enable);
 int rh_tile_choice(int maxn, int batch, int* nb, int* rm, int* pth, int* tile);
 int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
                     int* iters_host, double* resid_host, hipStream_t st);

@@ -1,26 +1,40 @@
 // Roberts-Higham iteration S_{n+1} = (S_n + S_n^{-1}) / 2 (Eq. (4)) for a
 // batch of dense complex matrices of uneven sizes, on gfx950.
 //
-// The inverse is an out-of-place blocked Gauss-Jordan elimination with
-// partial pivoting.  For each panel of NB columns:
-//  * k_gj_panel (one 1024-thread workgroup per matrix) eliminates the panel
-//    columns in registers: pivot search over the rows not yet used, row
-//    bookkeeping in LDS (the rows themselves are not moved), and writes the
-//    transformed panel M in pivot order plus the panel's row permutation;
-//  * k_gj_update applies the rank-NB update to every other column,
-//      new[pos][j] = (pos in panel ? 0 : old[src(pos)][j]) + sum_t M[pos][t] old[src(c0 + t)][j],
-//    reading the previous buffer and writing the other one (ping-pong), so
-//    no workgroup ever reads a row another one is writing.
-// The panel's thread count (and so rows per thread) and the update's tile
-// are chosen per matrix-size class by timing every feasible pair once (the
-// autotuner below); none of them changes the arithmetic: the pivot is the
-// largest candidate with ties to the smaller position whatever the thread
-// count, and every element sums its panel terms in the same order whatever
-// the tile, so the choice never changes a bit of the result.
-// k_rh_combine undoes the accumulated row permutation as a column
-// permutation of the inverse, forms the average (optionally with a positive
-// scale mu, which leaves the limit unchanged) and emits partial sums of
-// |S_{n+1} - S_n|_F^2 and |S_{n+1}|_F^2 for the host's stopping test.
+// Orders up to 128 run every iteration in one launch per batch (k_rh_small,
+// below).  Larger ones invert each iterate by a blocked Gauss-Jordan
+// elimination with partial pivoting in which rows are never moved: posof[r]
+// is the column whose pivot row is r (-1 while r is unused) and rowof[c] the
+// pivot row of column c, and the eliminated matrix X holds
+// inv(S)[posof[r]][rowof[c]] at (r, c).  For each panel of NB columns
+// c0 .. c0 + NB - 1 of the buffer `old`:
+//  * k_gjp (one workgroup per matrix) eliminates the panel columns in
+//    registers, each thread owning whole panel rows (loaded and stored
+//    through LDS, sixteen threads to a row, where the panel fits).  Per
+//    column: every lane forms a 32-bit pivot key of its unused rows (the
+//    magnitude's float bits with the low 13 bits replaced by 8191 - row, so
+//    the largest magnitude to ten mantissa bits wins and ties go to the
+//    smaller row), a DPP maximum gives each wave's largest key, which goes to
+//    LDS; after a barrier every thread knows the pivot row, whose owner
+//    writes it to LDS; after a second barrier every thread updates its own
+//    rows with it.  The transformed panel M (rows in place) goes to the
+//    panel columns of `new`.
+//  * k_gju applies the panel to every other column on the FP64 matrix cores
+//    (v_mfma_f64_16x16x4f64, four real products per complex one):
+//      new[r][j] = (posof[r] in the panel ? 0 : old[r][j]) + sum_t M[r][t] old[rowof[c0 + t]][j],
+//    reading `old` and writing `new` (ping-pong), so no workgroup reads a
+//    row that another one writes.
+// The panel's thread count (and so rows per thread) and the update's output
+// tile are chosen per matrix-size class by timing every feasible pair once
+// (the autotuner below).  None of them changes the arithmetic: the pivot key
+// is independent of the thread layout, every panel row sees the same
+// operations in the same order, and every output element of the update is
+// accumulated by the same matrix-core chain at the same position of a
+// 16 x 16 tile whatever the output tile; so the choice never changes a bit
+// of the result.  k_gjcombine maps X back through posof and rowof, forms the
+// average (optionally with a positive scale mu, which leaves the limit
+// unchanged) and emits partial sums of |S_{n+1} - S_n|_F^2 and
+// |S_{n+1}|_F^2 for the host's stopping test.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -31,9 +45,19 @@
 namespace nk {
 
 constexpr int PT = 1024;  // largest panel thread count
-constexpr int UT = 256;   // update threads (16 x 16), each (T / 16)^2 elements of a T x T tile
+constexpr int UT = 256;   // update threads: four waves of 16 x 16 matrix-core tiles
 
 __device__ __forceinline__ double cabs1(C64 a) { return fabs(a.re) + fabs(a.im); }
+
+// 1 / a = conj(a) / |a|^2 with a first scaled by a power of two (exact), so
+// that |a|^2 neither overflows nor underflows: one division
+__device__ __forceinline__ C64 crecip1(C64 a) {
+  int e;
+  (void)frexp(fmax(fabs(a.re), fabs(a.im)), &e);
+  const double ar = ldexp(a.re, -e), ai = ldexp(a.im, -e);
+  const double q = 1.0 / (ar * ar + ai * ai);
+  return mk(ldexp(ar * q, -e), ldexp(-ai * q, -e));
+}
 
 __device__ __forceinline__ C64 cinv(C64 a) {
   // 1 / a, scaled to avoid overflow in |a|^2
@@ -43,11 +67,40 @@ __device__ __forceinline__ C64 cinv(C64 a) {
   return mk(ar / d, -ai / d);
 }
 
+typedef double nk_d4 __attribute__((ext_vector_type(4)));
+
+// the 32-bit pivot key of a panel row r < 4096 (never zero)
+__device__ __forceinline__ unsigned gj_key(double mag, int r) {
+  if (!(mag >= 0.0)) mag = 0.0;  // a NaN entry counts as a zero pivot, so some row is always chosen
+  return (__float_as_uint((float)mag) & ~0x1FFFu) | (unsigned)(8191 - r);
+}
+
+// the largest of a 32-bit value over the 64 lanes of a wave (DPP row shifts,
+// then the row broadcasts), in every lane
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// LDS staging of the whole panel (coalesced loads and stores) when it fits
 template <int NB, int RM, int PTH>
-__global__ void __launch_bounds__(PTH) k_gj_panel(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
-                                                 int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
-                                                 int* __restrict__ p2r_b, int* __restrict__ perm_b,
-                                                 double* __restrict__ logdet, int* __restrict__ sing) {
+struct GJStage {
+  static constexpr bool on = (size_t)PTH * RM * (NB + 1) * sizeof(C64) <= 144 * 1024;
+  static constexpr int rows = on ? PTH * RM : 1;
+};
+
+template <int NB, int RM, int PTH>
+__global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
+                                            int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
+                                            int* __restrict__ rowof_b, int* __restrict__ posof_b,
+                                            double* __restrict__ logdet, int* __restrict__ sing) {
+  constexpr int NW = PTH / 64;
+  using SG = GJStage<NB, RM, PTH>;
   const int b = blockIdx.x;
   const int n = nvec[b];
   if (!active[b] || c0 >= n) return;
@@ -55,227 +108,230 @@ __global__ void __launch_bounds__(PTH) k_gj_panel(int ld, const int* __restrict_
   const size_t off = (size_t)b * ld * ld;
   const C64* Aold = Aold_b + off;
   C64* Anew = Anew_b + off;
-  int* p2r = p2r_b + (size_t)b * ld;
-  int* perm = perm_b + (size_t)b * ld;
-
-  __shared__ int s_p2r[PTH * RM];
-  __shared__ int s_r2p[PTH * RM];
-  __shared__ C64 s_prow[NB];
-  __shared__ double s_val[PTH / 64];
-  __shared__ int s_pos[PTH / 64];
-  __shared__ double s_ld;
-  __shared__ int s_sing;
-
+  int* rowof = rowof_b + (size_t)b * ld;
+  int* posof = posof_b + (size_t)b * ld;
+  __shared__ unsigned s_key[2][NW];
+  __shared__ C64 s_prow[2][NB];
+  __shared__ int s_piv[NB];  // pivot rows of the panel, written to memory after the last column
+  __shared__ C64 s_panel[SG::rows][NB + 1];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   C64 a[RM][NB];
+  bool used[RM];
+  if constexpr (SG::on) {
+    // sixteen consecutive threads read one row's NB entries (contiguous)
+    for (int e = tid; e < SG::rows * NB; e += PTH) {
+      const int r = e / NB, t = e % NB;
+      s_panel[r][t] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+  }
 #pragma unroll
   for (int m = 0; m < RM; ++m) {
     const int r = tid + m * PTH;
+    used[m] = !(r < n) || posof[r] >= 0;  // rows past the order never pivot
 #pragma unroll
-    for (int t = 0; t < NB; ++t) a[m][t] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
+    for (int t = 0; t < NB; ++t) {
+      if constexpr (SG::on)
+        a[m][t] = s_panel[r][t];
+      else
+        a[m][t] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
+    }
   }
-  for (int r = tid; r < n; r += PTH) {
-    s_p2r[r] = r;
-    s_r2p[r] = r;
-  }
-  if (tid == 0) {
-    s_ld = 0.0;
-    s_sing = 0;
-  }
-  __syncthreads();
-
+  // |det| of the panel's pivots as a running mantissa and binary exponent
+  double dm = 1.0;
+  int de = 0, bad = 0;
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     if (t < nbe) {
-      const int c = c0 + t;
-      double best = -1.0;
-      int bpos = 0x7fffffff;
+      const int par = t & 1;
+      // 1. every wave's largest key, then (after a barrier) the block's
+      unsigned key = 0;
+#pragma unroll
+      for (int m = 0; m < RM; ++m)
+        if (!used[m]) {
+          const unsigned kk = gj_key(cabs1(a[m][t]), tid + m * PTH);
+          key = kk > key ? kk : key;
+        }
+      const unsigned wmax = wave_max_u32(key);
+      if (lane == 0) s_key[par][wid] = wmax;
+      __syncthreads();
+      unsigned best = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const unsigned kw = s_key[par][w];
+        best = kw > best ? kw : best;
+      }
+      // while t < n - c0 an unused row remains, so best != 0; a zero key
+      // would only leave pr = -1 (no row replaced) and a zero multiplier
+      const int pr = best ? 8191 - (int)(best & 0x1FFFu) : -1;
+      // 2. the pivot row's owner hands its row to every thread
+#pragma unroll
+      for (int m = 0; m < RM; ++m)
+        if (tid + m * PTH == pr)
+#pragma unroll
+          for (int u = 0; u < NB; ++u) s_prow[par][u] = a[m][u];
+      if (tid == 0) s_piv[t] = pr;
+      __syncthreads();
+      const C64 piv = best ? s_prow[par][t] : mk(0.0, 0.0);
+      const bool nz = cabs1(piv) > 0.0;
+      if (!nz) bad = 1;
+      const C64 d = nz ? crecip1(piv) : mk(0.0, 0.0);
+      if (nz) {
+        int ex;
+        dm = frexp(dm * norm2(piv), &ex);
+        de += ex;
+      }
+      // 3. one branch-free update for every row: a[u] = keep * a[u] - g * p[u]
+      // with p the pivot row (p[t] replaced by 1) and
+      //   other rows: keep = 1 (0 in column t), g = a[t] / piv, so column t
+      //               becomes -a[t] / piv;
+      //   pivot row:  keep = 0, g = -1 / piv, so the row becomes p / piv
+      //               with 1 / piv in column t
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const int r = tid + m * PTH;
-        if (r < n) {
-          const int pos = s_r2p[r];
-          double v = cabs1(a[m][t]);
-          if (!(v >= 0.0)) v = 0.0;  // a NaN entry counts as a zero pivot, so some row is always chosen
-          if (pos >= c && (v > best || (v == best && pos < bpos))) {
-            best = v;
-            bpos = pos;
-          }
+        const bool isp = tid + m * PTH == pr;
+        const C64 fd = cmul(a[m][t], d);
+        const C64 g = isp ? mk(-d.re, -d.im) : fd;
+        const double keep = isp ? 0.0 : 1.0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          const C64 p = (u == t) ? mk(1.0, 0.0) : s_prow[par][u];
+          const double kr = (u == t) ? 0.0 : keep * a[m][u].re, ki = (u == t) ? 0.0 : keep * a[m][u].im;
+          a[m][u] = mk(fma(g.im, p.im, fma(-g.re, p.re, kr)), fma(-g.im, p.re, fma(-g.re, p.im, ki)));
         }
+        if (isp) used[m] = true;
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o, 64);
-        const int op = __shfl_xor(bpos, o, 64);
-        if (ov > best || (ov == best && op < bpos)) {
-          best = ov;
-          bpos = op;
-        }
-      }
-      if (lane == 0) {
-        s_val[wid] = best;
-        s_pos[wid] = bpos;
-      }
-      __syncthreads();
-      best = s_val[0];
-      bpos = s_pos[0];
-#pragma unroll
-      for (int w = 1; w < PTH / 64; ++w) {
-        const double ov = s_val[w];
-        const int op = s_pos[w];
-        if (ov > best || (ov == best && op < bpos)) {
-          best = ov;
-          bpos = op;
-        }
-      }
-      const int p = bpos < n ? bpos : c;  // (position c is always a candidate)
-      const int pr = s_p2r[p];
-      const int rc = s_p2r[c];
-      if ((pr & (PTH - 1)) == tid) {
-#pragma unroll
-        for (int m = 0; m < RM; ++m) {
-          if (m == pr / PTH) {
-            const C64 piv = a[m][t];
-            // a zero pivot flags the matrix as singular; the elimination
-            // goes on with a zero multiplier instead of 1/0, so no NaN
-            // spreads through the rest of the panel
-            const bool nz = best > 0.0;
-            if (!nz) s_sing = 1;
-            const C64 d = nz ? cinv(piv) : mk(0.0, 0.0);
-            if (nz) s_ld += log(sqrt(piv.re * piv.re + piv.im * piv.im));
-#pragma unroll
-            for (int u = 0; u < NB; ++u) s_prow[u] = (u == t) ? d : cmul(a[m][u], d);
-          }
-        }
-      }
-      __syncthreads();
-      if (tid == 0) {
-        s_p2r[c] = pr;
-        s_p2r[p] = rc;
-        s_r2p[pr] = c;
-        s_r2p[rc] = p;
-      }
-#pragma unroll
-      for (int m = 0; m < RM; ++m) {
-        const int r = tid + m * PTH;
-        if (r < n) {
-          if (r == pr) {
-#pragma unroll
-            for (int u = 0; u < NB; ++u) a[m][u] = s_prow[u];
-          } else {
-            const C64 f = a[m][t];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-              const C64 base = (u == t) ? mk(0.0, 0.0) : a[m][u];
-              a[m][u] = base - cmul(f, s_prow[u]);
-            }
-          }
-        }
-      }
-      __syncthreads();
     }
   }
-  // M in pivot order, the panel's position -> source-row map, the running permutation
+  if constexpr (SG::on) {
+    __syncthreads();
 #pragma unroll
-  for (int m = 0; m < RM; ++m) {
-    const int r = tid + m * PTH;
-    if (r < n) {
-      const int pos = s_r2p[r];
+    for (int m = 0; m < RM; ++m)
 #pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t < nbe) Anew[(size_t)pos * ld + c0 + t] = a[m][t];
+      for (int t = 0; t < NB; ++t) s_panel[tid + m * PTH][t] = a[m][t];
+    __syncthreads();
+    for (int e = tid; e < SG::rows * NB; e += PTH) {
+      const int r = e / NB, t = e % NB;
+      if (r < n && t < nbe) Anew[(size_t)r * ld + c0 + t] = s_panel[r][t];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < RM; ++m) {
+      const int r = tid + m * PTH;
+      if (r < n)
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+          if (t < nbe) Anew[(size_t)r * ld + c0 + t] = a[m][t];
     }
   }
-  int pv[RM];
-#pragma unroll
-  for (int m = 0; m < RM; ++m) {
-    const int pos = tid + m * PTH;
-    pv[m] = pos < n ? perm[s_p2r[pos]] : 0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < RM; ++m) {
-    const int pos = tid + m * PTH;
-    if (pos < n) {
-      perm[pos] = pv[m];
-      p2r[pos] = s_p2r[pos];
+  if (tid < nbe) {
+    const int pr = s_piv[tid];
+    if (pr >= 0) {
+      rowof[c0 + tid] = pr;
+      posof[pr] = c0 + tid;
     }
   }
   if (tid == 0) {
-    logdet[b] += s_ld;
-    if (s_sing) sing[b] = 1;
+    logdet[b] += 0.5 * (log(dm) + de * 0.69314718055994530942);
+    if (bad) sing[b] = 1;
   }
 }
 
+// the rank-NB update of every column outside the panel, T x T output tile
+// per 256-thread workgroup: four waves in a 2 x 2 arrangement, each with
+// (T / 32)^2 sub-tiles of 16 x 16 on the matrix cores.  MFMA operand layout
+// (16 x 16 x 4, FP64): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16],
+// and accumulator element i of lane l is D[4 i + l / 16][l % 16].
 template <int NB, int T>
-__global__ void __launch_bounds__(UT) k_gj_update(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
-                                                  int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
-                                                  const int* __restrict__ p2r_b) {
+__global__ void __launch_bounds__(256) k_gju(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
+                                            int c0, const C64* __restrict__ Aold_b, C64* __restrict__ Anew_b,
+                                            const int* __restrict__ rowof_b, const int* __restrict__ posof_b) {
+  constexpr int SUB = T / 32;
   const int b = blockIdx.z;
   const int n = nvec[b];
   if (!active[b] || c0 >= n) return;
-  constexpr int E = T / 16;  // rows and columns per thread
   const int row0 = blockIdx.y * T, col0 = blockIdx.x * T;
   if (row0 >= n || col0 >= n) return;
   const int nbe = min(NB, n - c0);
   const size_t off = (size_t)b * ld * ld;
   const C64* Aold = Aold_b + off;
   C64* Anew = Anew_b + off;
-  const int* p2r = p2r_b + (size_t)b * ld;
-  __shared__ C64 sM[T][NB + 1];
-  __shared__ C64 sR[NB][T + 1];
-  __shared__ int sP[T];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < T * NB; e += UT) {
-    const int i = e / NB, t = e % NB;
-    const int pos = row0 + i;
-    sM[i][t] = (pos < n && t < nbe) ? Anew[(size_t)pos * ld + c0 + t] : mk(0.0, 0.0);
-  }
-  for (int e = tid; e < T * NB; e += UT) {
-    const int t = e / T, j = e % T;
-    const int col = col0 + j;
-    sR[t][j] = (t < nbe && col < n) ? Aold[(size_t)p2r[c0 + t] * ld + col] : mk(0.0, 0.0);
-  }
-  if (tid < T) sP[tid] = (row0 + tid < n) ? p2r[row0 + tid] : 0;
-  __syncthreads();
-  const int tx = tid & 15, ty = tid >> 4;
+  const int* rowof = rowof_b + (size_t)b * ld;
+  const int* posof = posof_b + (size_t)b * ld;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = row0 + (w >> 1) * 16 * SUB, wc = col0 + (w & 1) * 16 * SUB;
+  const int l16 = lane & 15, lq = lane >> 4;
+  nk_d4 are[SUB][SUB], aim[SUB][SUB];
 #pragma unroll
-  for (int ii = 0; ii < E; ++ii) {
-    const int i = ty * E + ii;
-    const int pos = row0 + i;
-    if (pos >= n) continue;
-    const bool inpanel = pos >= c0 && pos < c0 + nbe;
+  for (int si = 0; si < SUB; ++si)
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int j = tx + 16 * q;
-      const int col = col0 + j;
-      if (col >= n || (col >= c0 && col < c0 + nbe)) continue;
-      C64 acc = inpanel ? mk(0.0, 0.0) : Aold[(size_t)sP[i] * ld + col];
-#pragma unroll
-      for (int t = 0; t < NB; ++t) acc = acc + cmul(sM[i][t], sR[t][j]);
-      Anew[(size_t)pos * ld + col] = acc;
+    for (int sj = 0; sj < SUB; ++sj) {
+      are[si][sj] = nk_d4{0.0, 0.0, 0.0, 0.0};
+      aim[si][sj] = nk_d4{0.0, 0.0, 0.0, 0.0};
     }
+#pragma unroll
+  for (int kk = 0; kk < NB / 4; ++kk) {
+    const int t = kk * 4 + lq;
+    const bool tin = t < nbe;
+    const int src = tin ? rowof[c0 + t] : 0;
+    C64 am[SUB], bm[SUB];
+#pragma unroll
+    for (int si = 0; si < SUB; ++si) {
+      const int r = wr + si * 16 + l16;
+      am[si] = (tin && r < n) ? Anew[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int sj = 0; sj < SUB; ++sj) {
+      const int c = wc + sj * 16 + l16;
+      bm[sj] = (tin && c < n) ? Aold[(size_t)src * ld + c] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int si = 0; si < SUB; ++si)
+#pragma unroll
+      for (int sj = 0; sj < SUB; ++sj) {
+        are[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[si].re, bm[sj].re, are[si][sj], 0, 0, 0);
+        are[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-am[si].im, bm[sj].im, are[si][sj], 0, 0, 0);
+        aim[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[si].re, bm[sj].im, aim[si][sj], 0, 0, 0);
+        aim[si][sj] = __builtin_amdgcn_mfma_f64_16x16x4f64(am[si].im, bm[sj].re, aim[si][sj], 0, 0, 0);
+      }
   }
+#pragma unroll
+  for (int si = 0; si < SUB; ++si)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wr + si * 16 + 4 * i + lq;
+      if (r >= n) continue;
+      const int p = posof[r];
+      const bool keep = !(p >= c0 && p < c0 + nbe);
+#pragma unroll
+      for (int sj = 0; sj < SUB; ++sj) {
+        const int c = wc + sj * 16 + l16;
+        if (c >= n || (c >= c0 && c < c0 + nbe)) continue;
+        const C64 base = keep ? Aold[(size_t)r * ld + c] : mk(0.0, 0.0);
+        Anew[(size_t)r * ld + c] = base + mk(are[si][sj][i], aim[si][sj][i]);
+      }
+    }
 }
 
-__global__ void k_rh_start(int ld, int batch, const int* __restrict__ nvec, const int* __restrict__ active,
-                           int* __restrict__ perm_b, double* __restrict__ logdet) {
+__global__ void k_gjstart(int ld, int batch, const int* __restrict__ nvec, const int* __restrict__ active,
+                          int* __restrict__ posof_b, double* __restrict__ logdet) {
   const int b = blockIdx.y;
   if (!active[b]) return;
   const int n = nvec[b];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    perm_b[(size_t)b * ld + i] = i;
+    posof_b[(size_t)b * ld + i] = -1;
   if (blockIdx.x == 0 && threadIdx.x == 0) logdet[b] = 0.0;
 }
 
 // G0/G1: the ping-pong buffers; a matrix of order n ends its elimination in
 // the buffer of its own last panel, (ceil(n / nb) - 1) % 2.
-__global__ void __launch_bounds__(256) k_rh_combine(int ld, int nb, const int* __restrict__ nvec,
-                                                    const int* __restrict__ active, const C64* __restrict__ G0,
-                                                    const C64* __restrict__ G1,
-                                                    C64* __restrict__ X_b, const int* __restrict__ perm_b,
-                                                    const double* __restrict__ logdet, int scaling,
-                                                    const double* __restrict__ mu_in, double* __restrict__ part) {
+// S_{n+1}[posof[r]][rowof[c]] = (mu S_n[..][..] + X[r][c] / mu) / 2
+__global__ void __launch_bounds__(256) k_gjcombine(int ld, int nb, const int* __restrict__ nvec,
+                                                   const int* __restrict__ active, const C64* __restrict__ G0,
+                                                   const C64* __restrict__ G1, C64* __restrict__ X_b,
+                                                   const int* __restrict__ rowof_b, const int* __restrict__ posof_b,
+                                                   const double* __restrict__ logdet, int scaling,
+                                                   const double* __restrict__ mu_in, double* __restrict__ part) {
   const int b = blockIdx.y;
   const int n = nvec[b];
   double dsum = 0.0, nsum = 0.0;
@@ -288,13 +344,14 @@ __global__ void __launch_bounds__(256) k_rh_combine(int ld, int nb, const int* _
     const int npan = (n + nb - 1) / nb;
     const C64* G = (((npan - 1) & 1) ? G1 : G0) + off;
     C64* X = X_b + off;
-    const int* perm = perm_b + (size_t)b * ld;
+    const int* rowof = rowof_b + (size_t)b * ld;
+    const int* posof = posof_b + (size_t)b * ld;
     const size_t nn = (size_t)n * n;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < nn; e += (size_t)gridDim.x * 256) {
-      const int i = (int)(e / n), p = (int)(e % n);
-      const size_t xi = (size_t)i * ld + perm[p];
+      const int r = (int)(e / n), c = (int)(e % n);
+      const size_t xi = (size_t)posof[r] * ld + rowof[c];
       const C64 xs = mu * X[xi];
-      const C64 s = 0.5 * (xs + imu * G[(size_t)i * ld + p]);
+      const C64 s = 0.5 * (xs + imu * G[(size_t)r * ld + c]);
       X[xi] = s;
       const C64 d = s - xs;
       dsum += norm2(d);
@@ -317,24 +374,158 @@ __global__ void __launch_bounds__(256) k_rh_combine(int ld, int nb, const int* _
   }
 }
 
-// r_b = |S (S e_1) - e_1| per matrix (one workgroup per matrix)
-__global__ void __launch_bounds__(256) k_rh_resid(int ld, const int* __restrict__ nvec, const C64* __restrict__ S_b,
-                                                  double* __restrict__ out) {
+
+// r_b = |S (S e_1) - e_1| per matrix, in two steps: one wave per row i forms
+// |(S (S e_1))_i - delta_i0|^2 (lanes over the row, a fixed-order wave sum),
+// then one workgroup per matrix sums the rows in row order
+__global__ void __launch_bounds__(256) k_rh_resid_rows(int ld, const int* __restrict__ nvec,
+                                                       const C64* __restrict__ S_b, double* __restrict__ rows) {
+  const int b = blockIdx.y;
+  const int n = nvec[b];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const C64* S = S_b + (size_t)b * ld * ld;
+  double re = 0.0, im = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    const C64 t = cmul(S[(size_t)i * ld + j], S[(size_t)j * ld]);
+    re += t.re;
+    im += t.im;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  if (lane == 0) {
+    if (i == 0) re -= 1.0;
+    rows[(size_t)b * ld + i] = re * re + im * im;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rh_resid_sum(int ld, const int* __restrict__ nvec,
+                                                      const double* __restrict__ rows, double* __restrict__ out) {
   const int b = blockIdx.x;
   const int n = nvec[b];
-  const C64* S = S_b + (size_t)b * ld * ld;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) {
-    C64 t = mk(0.0, 0.0);
-    for (int j = 0; j < n; ++j) t = t + cmul(S[(size_t)i * ld + j], S[(size_t)j * ld]);
-    if (i == 0) t.re -= 1.0;
-    acc += norm2(t);
-  }
+  for (int i = threadIdx.x; i < n; i += 256) acc += rows[(size_t)b * ld + i];
   __shared__ double sh[4];
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) out[b] = sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
+}
+
+// ---------------------------------------------------------------------------
+// Newton-Schulz tail of the iteration (an option of this library, not the
+// paper's): once |I - S_n^2|_F < 1/2, X <- X (3 I - X^2) / 2 converges
+// quadratically to the same sgn(S_n) = sgn(S_0) (with R = I - X^2 the next
+// R is (3/4) R^2 + (1/4) R^3, so |R| falls monotonically below 1/2), and
+// needs two matrix products per step instead of an inversion.
+// k_ns_gemm: C = A B for n x n complex matrices, 32 x 32 output tile per
+// 256-thread workgroup (2 x 2 waves of 16 x 16 matrix-core tiles), K in
+// blocks of 16 staged through LDS with the next block's loads in flight
+// during the current block's products.
+//  MODE 0: C = 3 I - A B, partial sums of |I - A B|_F^2 (A = B = S);
+//  MODE 1: C = (A B) / 2, partial sums of |C - A|_F^2 and |C|_F^2
+//          (A = S, B = 3 I - S^2, so C is the next iterate).
+// Partial sums: one pair per workgroup at part[(b * tiles^2 + tile) * 2].
+template <int MODE>
+__global__ void __launch_bounds__(256) k_ns_gemm(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
+                                                const C64* __restrict__ A_b, const C64* __restrict__ B_b,
+                                                C64* __restrict__ C_b, double* __restrict__ part) {
+  const int b = blockIdx.z;
+  const int n = nvec[b];
+  const int tile = blockIdx.y * gridDim.x + blockIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  __shared__ C64 sA[32][17];
+  __shared__ C64 sB[16][33];
+  __shared__ double sh[2][4];
+  const bool live = active[b] && blockIdx.y * 32 < n && blockIdx.x * 32 < n;
+  if (live) {
+    const size_t off = (size_t)b * ld * ld;
+    const C64* A = A_b + off;
+    const C64* B = B_b + off;
+    C64* C = C_b + off;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int row0 = blockIdx.y * 32, col0 = blockIdx.x * 32;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+    nk_d4 are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
+    C64 ra[2], rb[2];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int e = tid + 256 * q;
+        const int ar = row0 + e / 16, ak = k0 + e % 16;
+        ra[q] = (ar < n && ak < n) ? A[(size_t)ar * ld + ak] : mk(0.0, 0.0);
+        const int bk = k0 + e / 32, bc = col0 + e % 32;
+        rb[q] = (bk < n && bc < n) ? B[(size_t)bk * ld + bc] : mk(0.0, 0.0);
+      }
+    };
+    load(0);
+    for (int k0 = 0; k0 < n; k0 += 16) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int e = tid + 256 * q;
+        sA[e / 16][e % 16] = ra[q];
+        sB[e / 32][e % 32] = rb[q];
+      }
+      __syncthreads();
+      if (k0 + 16 < n) load(k0 + 16);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const C64 am = sA[wr + l16][kk * 4 + lq];
+        const C64 bm = sB[kk * 4 + lq][wc + l16];
+        are = __builtin_amdgcn_mfma_f64_16x16x4f64(am.re, bm.re, are, 0, 0, 0);
+        are = __builtin_amdgcn_mfma_f64_16x16x4f64(-am.im, bm.im, are, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(am.re, bm.im, aim, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(am.im, bm.re, aim, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = row0 + wr + 4 * i + lq, c = col0 + wc + l16;
+      if (r >= n || c >= n) continue;
+      const C64 p = mk(are[i], aim[i]);
+      if (MODE == 0) {
+        const double dg = r == c ? 1.0 : 0.0;
+        C[(size_t)r * ld + c] = mk(3.0 * dg - p.re, -p.im);
+        s0 += norm2(mk(dg - p.re, -p.im));
+      } else {
+        const C64 g = 0.5 * p;
+        C[(size_t)r * ld + c] = g;
+        s0 += norm2(g - A[(size_t)r * ld + c]);
+        s1 += norm2(g);
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    s1 += __shfl_xor(s1, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = s0;
+    sh[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const size_t p = ((size_t)b * gridDim.x * gridDim.y + tile) * 2;
+    part[p + 0] = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    part[p + 1] = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+  }
+}
+
+// S <- G for the matrices in the Newton-Schulz set
+__global__ void k_ns_copy(int ld, const int* __restrict__ nvec, const int* __restrict__ active,
+                          const C64* __restrict__ G_b, C64* __restrict__ S_b) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const int n = nvec[b];
+  const size_t off = (size_t)b * ld * ld, nn = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = off + (e / n) * ld + (e % n);
+    S_b[i] = G_b[i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -539,21 +730,25 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
 // ---------------------------------------------------------------------------
 namespace {
 std::mutex g_rh_mu;
-DevBuf g_G0, g_G1, g_int, g_dbl, g_mu, g_sched;
+DevBuf g_G0, g_G1, g_int, g_dbl, g_mu, g_sched, g_nsp;
+// the Newton-Schulz tail of the large path (nk_rh_newton_schulz); on by default
+int g_ns_tail = 1;
 }  // namespace
 
 template <int NB, int RM, int PTH, int T>
 static void launch_inverse(int batch, int ld, int maxn, const int* nvec, const int* act, const C64* S, C64* G0,
-                           C64* G1, int* p2r, int* perm, double* logdet, int* sing, hipStream_t st) {
+                           C64* G1, int* rowof, int* posof, double* logdet, int* sing, hipStream_t st) {
   const C64* cur = S;
   int which = 0;
   const int tiles = (maxn + T - 1) / T;
+  hipLaunchKernelGGL(k_gjstart, dim3((maxn + 255) / 256, batch), dim3(256), 0, st, ld, batch, nvec, act, posof,
+                     logdet);
   for (int c0 = 0; c0 < maxn; c0 += NB) {
     C64* nxt = which ? G1 : G0;
-    hipLaunchKernelGGL((k_gj_panel<NB, RM, PTH>), dim3(batch), dim3(PTH), 0, st, ld, nvec, act, c0, cur, nxt, p2r,
-                       perm, logdet, sing);
-    hipLaunchKernelGGL((k_gj_update<NB, T>), dim3(tiles, tiles, batch), dim3(UT), 0, st, ld, nvec, act, c0, cur, nxt,
-                       p2r);
+    hipLaunchKernelGGL((k_gjp<NB, RM, PTH>), dim3(batch), dim3(PTH), 0, st, ld, nvec, act, c0, cur, nxt, rowof,
+                       posof, logdet, sing);
+    hipLaunchKernelGGL((k_gju<NB, T>), dim3(tiles, tiles, batch), dim3(UT), 0, st, ld, nvec, act, c0, cur, nxt,
+                       rowof, posof);
     cur = nxt;
     which ^= 1;
   }
@@ -561,24 +756,24 @@ static void launch_inverse(int batch, int ld, int maxn, const int* nvec, const i
 
 // The launch shapes of the blocked inverse: panel threads x rows per thread
 // (which must cover ld) and the update tile.  The panel width is not among
-// the choices: it sets the grouping of the update sums, 16 up to ld = 1024
-// and 8 above, fixed by ld alone.
+// the choices: it sets the grouping of the update sums, 16 up to ld = 1024,
+// 8 up to 2048 and 4 above, fixed by ld alone.
 struct GJShape {
   int nb, rm, pth, tile;
 };
 // every instantiated shape (the panel keeps rm x nb complex values per
 // thread in registers, so rm x nb x 4 VGPRs must fit beside the rest at
-// pth / 256 waves per SIMD; 4 rows of 16 would live in scratch memory)
+// pth / 256 waves per SIMD: at most 64 at 1024 threads, 128 at 512)
 #define NK_GJ_SHAPES(X)                                                                                      \
   X(16, 1, 256, 32) X(16, 1, 256, 64) X(16, 1, 512, 32) X(16, 1, 512, 64) X(16, 1, 1024, 32)                \
   X(16, 1, 1024, 64) X(16, 2, 256, 32) X(16, 2, 256, 64) X(16, 2, 512, 32) X(16, 2, 512, 64)                \
-  X(8, 2, 1024, 32) X(8, 2, 1024, 64) X(8, 4, 512, 32)                                                      \
-  X(8, 4, 512, 64) X(8, 4, 1024, 32) X(8, 4, 1024, 64)
+  X(8, 2, 1024, 32) X(8, 2, 1024, 64) X(8, 4, 512, 32) X(8, 4, 512, 64)                                     \
+  X(4, 4, 1024, 32) X(4, 4, 1024, 64)
 #define NK_GJ_ENTRY(NB, RM, PTH, T) {NB, RM, PTH, T},
 constexpr GJShape kGJShapes[] = {NK_GJ_SHAPES(NK_GJ_ENTRY)};
 #undef NK_GJ_ENTRY
 
-static int gj_nb(int ld) { return ld <= PT ? 16 : 8; }
+static int gj_nb(int ld) { return ld <= PT ? 16 : ld <= 2 * PT ? 8 : 4; }
 
 static bool gj_feasible(const GJShape& sh, int ld) {
   for (const GJShape& k : kGJShapes)
@@ -589,11 +784,11 @@ static bool gj_feasible(const GJShape& sh, int ld) {
 
 // one blocked inverse with a shape that gj_feasible accepts for ld
 static void launch_inverse_shape(const GJShape& sh, int batch, int ld, int maxn, const int* nvec, const int* act,
-                                 const C64* S, C64* G0, C64* G1, int* p2r, int* perm, double* logdet, int* sing,
+                                 const C64* S, C64* G0, C64* G1, int* rowof, int* posof, double* logdet, int* sing,
                                  hipStream_t st) {
 #define NK_GJ_CALL(NB, RM, PTH, T)                                                                            \
   if (sh.nb == NB && sh.rm == RM && sh.pth == PTH && sh.tile == T)                                            \
-    return launch_inverse<NB, RM, PTH, T>(batch, ld, maxn, nvec, act, S, G0, G1, p2r, perm, logdet, sing, st);
+    return launch_inverse<NB, RM, PTH, T>(batch, ld, maxn, nvec, act, S, G0, G1, rowof, posof, logdet, sing, st);
   NK_GJ_SHAPES(NK_GJ_CALL)
 #undef NK_GJ_CALL
 }
@@ -612,7 +807,7 @@ static int gj_key(int maxn, int batch) {
 // the current iterate with every feasible shape (the results are discarded;
 // every shape computes the same bits)
 static int gj_choose(int batch, int ld, int maxn, const int* nvec, const int* act, const C64* S, C64* G0, C64* G1,
-                     int* p2r, int* perm, double* logdet, int* sing, hipStream_t st, GJShape* out) {
+                     int* rowof, int* posof, double* logdet, int* sing, hipStream_t st, GJShape* out) {
   if (g_gj_force.pth) {
     const GJShape f{gj_nb(ld), g_gj_force.rm, g_gj_force.pth, g_gj_force.tile};
     if (gj_feasible(f, ld)) {
@@ -635,10 +830,8 @@ static int gj_choose(int batch, int ld, int maxn, const int* nvec, const int* ac
     if (!gj_feasible(sh, ld)) continue;
     float ms = 0.f;
     for (int rep = 0; rep < 2; ++rep) {  // the first run of a shape warms it up
-      hipLaunchKernelGGL(k_rh_start, dim3((maxn + 255) / 256, batch), dim3(256), 0, st, ld, batch, nvec, act, perm,
-                         logdet);
       NK_HIP(hipEventRecord(e0, st));
-      launch_inverse_shape(sh, batch, ld, maxn, nvec, act, S, G0, G1, p2r, perm, logdet, sing, st);
+      launch_inverse_shape(sh, batch, ld, maxn, nvec, act, S, G0, G1, rowof, posof, logdet, sing, st);
       NK_HIP(hipEventRecord(e1, st));
       NK_HIP(hipEventSynchronize(e1));
       NK_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -670,6 +863,13 @@ static int rh_outcome(int batch, const int* state, int maxit) {
       return NK_WARN_NOTCONV;
     }
   return NK_OK;
+}
+
+int rh_newton_schulz(int enable) {
+  std::lock_guard<std::mutex> lock(g_rh_mu);
+  const int old = g_ns_tail;
+  g_ns_tail = enable ? 1 : 0;
+  return old;
 }
 
 int rh_tile_force(int rm, int pth, int tile) {
@@ -712,16 +912,17 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   const size_t mb = (size_t)batch * ld * ld * sizeof(C64);
   const int nbl = 64;
   if (g_G0.ensure(mb) || g_G1.ensure(mb) || g_int.ensure((size_t)batch * (2 * ld + 4) * sizeof(int)) ||
-      g_dbl.ensure((size_t)batch * (2 * nbl + 4) * sizeof(double)) || g_mu.ensure((size_t)batch * sizeof(double)))
+      g_dbl.ensure((size_t)batch * (2 * nbl + 4 + ld) * sizeof(double)) || g_mu.ensure((size_t)batch * sizeof(double)))
     return NK_ENOMEM;
   int* nvec = g_int.as<int>();
   int* act = nvec + batch;
   int* sing = act + batch;
-  int* p2r = sing + batch;
-  int* perm = p2r + (size_t)batch * ld;
+  int* rowof = sing + batch;
+  int* posof = rowof + (size_t)batch * ld;
   double* logdet = g_dbl.as<double>();
   double* resid = logdet + batch;
   double* part = resid + batch;
+  double* rrows = part + (size_t)batch * 2 * nbl;  // per-row terms of the residual
   double* mu_dev = g_mu.as<double>();
 
   int maxn = 0;
@@ -754,7 +955,8 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     NK_HIP(hipMemcpyAsync(iters_host, act, batch * sizeof(int), hipMemcpyDeviceToHost, st));
     NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
     if (resid_host) {
-      hipLaunchKernelGGL(k_rh_resid, dim3(batch), dim3(256), 0, st, ld, nvec, S, resid);
+      hipLaunchKernelGGL(k_rh_resid_rows, dim3((maxn + 3) / 4, batch), dim3(256), 0, st, ld, nvec, S, rrows);
+      hipLaunchKernelGGL(k_rh_resid_sum, dim3(batch), dim3(256), 0, st, ld, nvec, rrows, resid);
       NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
     }
     NK_HIP(hipStreamSynchronize(st));
@@ -767,8 +969,18 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     iters_host[b] = 0;
   }
   NK_HIP(hipMemcpyAsync(act, act_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+  // Newton-Schulz tail: workspace and per-matrix state (0: inversion steps,
+  // 1: Newton-Schulz steps, entered once |I - S^2|_F < 1/2)
+  const int ntile = (maxn + 31) / 32;
+  const size_t nsp = (size_t)batch * ntile * ntile * 2;
+  if (g_nsp.ensure(nsp * sizeof(double) + (size_t)batch * sizeof(int))) return NK_ENOMEM;
+  double* nspart = g_nsp.as<double>();
+  int* act_ns = reinterpret_cast<int*>(nspart + nsp);
+  std::vector<int> ns_h(batch, 0), try_h(batch, 0), gj_h(batch, 0);
+  std::vector<double> nsp_h(nsp);
+  const int ns_on = g_ns_tail;
   GJShape shape;
-  if (int e = gj_choose(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet, sing, st,
+  if (int e = gj_choose(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), rowof, posof, logdet, sing, st,
                         &shape))
     return e;
   NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
@@ -779,33 +991,82 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     NK_HIP(hipMemcpyAsync(sched_h.data(), mdev, sched_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     NK_HIP(hipStreamSynchronize(st));
   }
+  // the step at which a matrix may try the Newton-Schulz test: once its
+  // relative change has fallen below this (earlier tests would only fail)
+  const double ns_try = 0.05;
   for (int it = 1; it <= maxit; ++it) {
     bool any = false;
     for (int b = 0; b < batch; ++b) any = any || act_h[b];
     if (!any) break;
-    NK_HIP(hipMemcpyAsync(act, act_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
-    if (scaling == NK_RH_LEARNED) {
-      for (int b = 0; b < batch; ++b)
-        mu_h[b] = (mdev && it - 1 < mu_steps) ? sched_h[(size_t)b * mu_steps + (it - 1)] : -1.0;
-      NK_HIP(hipMemcpyAsync(mu_dev, mu_h.data(), batch * sizeof(double), hipMemcpyHostToDevice, st));
+    // 1. the Newton-Schulz test (and its first product) for matrices in the
+    //    tail or close enough to try it: T = 3 I - S^2, |I - S^2|_F
+    bool anytry = false;
+    for (int b = 0; b < batch; ++b) {
+      try_h[b] = (ns_on && act_h[b] && (ns_h[b] || prev[b] < ns_try)) ? 1 : 0;
+      anytry = anytry || try_h[b];
     }
-    hipLaunchKernelGGL(k_rh_start, dim3((maxn + 255) / 256, batch), dim3(256), 0, st, ld, batch, nvec, act, perm,
-                       logdet);
-    const int nbw = gj_nb(ld);
-    launch_inverse_shape(shape, batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), p2r, perm, logdet,
-                         sing, st);
-    const int rs = scaling == NK_RH_LEARNED ? NK_RH_LEARNED : (scaling == NK_RH_DET ? NK_RH_DET : NK_RH_NONE);
-    hipLaunchKernelGGL(k_rh_combine, dim3(nbl, batch), dim3(256), 0, st, ld, nbw, nvec, act, g_G0.as<C64>(),
-                       g_G1.as<C64>(), S, perm, logdet, rs, mu_dev, part);
-    NK_HIP(hipGetLastError());
-    NK_HIP(hipMemcpyAsync(part_h.data(), part, part_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (anytry) {
+      NK_HIP(hipMemcpyAsync(act_ns, try_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_ns_gemm<0>, dim3(ntile, ntile, batch), dim3(256), 0, st, ld, nvec, act_ns, S, S,
+                         g_G0.as<C64>(), nspart);
+      NK_HIP(hipGetLastError());
+      NK_HIP(hipMemcpyAsync(nsp_h.data(), nspart, nsp * sizeof(double), hipMemcpyDeviceToHost, st));
+      NK_HIP(hipStreamSynchronize(st));
+      for (int b = 0; b < batch; ++b) {
+        if (!try_h[b]) continue;
+        double r2 = 0.0;
+        for (size_t i = 0; i < (size_t)ntile * ntile; ++i) r2 += nsp_h[((size_t)b * ntile * ntile + i) * 2];
+        ns_h[b] = std::sqrt(r2) < 0.5 ? 1 : 0;
+      }
+    }
+    bool anyns = false, anygj = false;
+    for (int b = 0; b < batch; ++b) {
+      const int nsb = act_h[b] && ns_h[b];
+      try_h[b] = nsb;
+      gj_h[b] = act_h[b] && !nsb;
+      anyns = anyns || nsb;
+      anygj = anygj || gj_h[b];
+    }
+    // 2. Newton-Schulz step: G1 = S (3 I - S^2) / 2, then S <- G1
+    if (anyns) {
+      NK_HIP(hipMemcpyAsync(act_ns, try_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_ns_gemm<1>, dim3(ntile, ntile, batch), dim3(256), 0, st, ld, nvec, act_ns, S,
+                         g_G0.as<C64>(), g_G1.as<C64>(), nspart);
+      hipLaunchKernelGGL(k_ns_copy, dim3(64, batch), dim3(256), 0, st, ld, nvec, act_ns, g_G1.as<C64>(), S);
+      NK_HIP(hipGetLastError());
+    }
+    // 3. inversion step: S <- (mu S + (mu S)^{-1}) / 2
+    if (anygj) {
+      NK_HIP(hipMemcpyAsync(act, gj_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+      if (scaling == NK_RH_LEARNED) {
+        for (int b = 0; b < batch; ++b)
+          mu_h[b] = (mdev && it - 1 < mu_steps) ? sched_h[(size_t)b * mu_steps + (it - 1)] : -1.0;
+        NK_HIP(hipMemcpyAsync(mu_dev, mu_h.data(), batch * sizeof(double), hipMemcpyHostToDevice, st));
+      }
+      const int nbw = gj_nb(ld);
+      launch_inverse_shape(shape, batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), rowof, posof, logdet,
+                           sing, st);
+      const int rs = scaling == NK_RH_LEARNED ? NK_RH_LEARNED : (scaling == NK_RH_DET ? NK_RH_DET : NK_RH_NONE);
+      hipLaunchKernelGGL(k_gjcombine, dim3(nbl, batch), dim3(256), 0, st, ld, nbw, nvec, act, g_G0.as<C64>(),
+                         g_G1.as<C64>(), S, rowof, posof, logdet, rs, mu_dev, part);
+      NK_HIP(hipGetLastError());
+      NK_HIP(hipMemcpyAsync(part_h.data(), part, part_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    if (anyns) NK_HIP(hipMemcpyAsync(nsp_h.data(), nspart, nsp * sizeof(double), hipMemcpyDeviceToHost, st));
     NK_HIP(hipStreamSynchronize(st));
     for (int b = 0; b < batch; ++b) {
       if (!act_h[b]) continue;
       double d = 0.0, nn = 0.0;
-      for (int i = 0; i < nbl; ++i) {
-        d += part_h[((size_t)b * nbl + i) * 2 + 0];
-        nn += part_h[((size_t)b * nbl + i) * 2 + 1];
+      if (ns_h[b]) {
+        for (size_t i = 0; i < (size_t)ntile * ntile; ++i) {
+          d += nsp_h[((size_t)b * ntile * ntile + i) * 2 + 0];
+          nn += nsp_h[((size_t)b * ntile * ntile + i) * 2 + 1];
+        }
+      } else {
+        for (int i = 0; i < nbl; ++i) {
+          d += part_h[((size_t)b * nbl + i) * 2 + 0];
+          nn += part_h[((size_t)b * nbl + i) * 2 + 1];
+        }
       }
       const double change = std::sqrt(d / nn);
       iters_host[b] = it;
@@ -816,7 +1077,8 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   std::vector<int> sing_h(batch);
   NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
   if (resid_host) {
-    hipLaunchKernelGGL(k_rh_resid, dim3(batch), dim3(256), 0, st, ld, nvec, S, resid);
+    hipLaunchKernelGGL(k_rh_resid_rows, dim3((maxn + 3) / 4, batch), dim3(256), 0, st, ld, nvec, S, rrows);
+    hipLaunchKernelGGL(k_rh_resid_sum, dim3(batch), dim3(256), 0, st, ld, nvec, rrows, resid);
     NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
   }
   NK_HIP(hipStreamSynchronize(st));

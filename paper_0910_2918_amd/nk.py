@@ -80,6 +80,8 @@ EXPORTS = (
     "nk_stencil_groups",
     "nk_rh_tile_force",
     "nk_rh_tile_choice",
+    "nk_rh_newton_schulz",
+    "nk_stream_device",
     "nk_apply_dw_noalloc_device",
     "nk_last_error",
     "nk_version",
@@ -194,6 +196,8 @@ def library():
                                               P(i32), P(C.c_double), vp]),
         "nk_stencil_groups": (C.c_int, [vp, i32, i32]),
         "nk_rh_tile_force": (C.c_int, [i32, i32, i32]),
+        "nk_rh_newton_schulz": (C.c_int, [i32]),
+        "nk_stream_device": (C.c_int, [i32, C.c_int64, vp, vp, vp, i32, vp]),
         "nk_rh_tile_choice": (C.c_int, [i32, i32, P(i32)]),
         "nk_last_error": (C.c_char_p, []),
         "nk_version": (C.c_char_p, []),
@@ -238,6 +242,17 @@ def _hptr(a: np.ndarray):
 def nk_stencil_groups(h, precision: int = 0, hermitian: bool = False) -> int:
     """Direction groups the autotuner chose for the stencil kernel (0 = not yet tuned)."""
     return _check(library().nk_stencil_groups(h, int(precision), 1 if hermitian else 0))
+
+
+def nk_stream_device(kind: int, a, b, c, blocks: int, stream=None) -> None:
+    """Streaming measurement kernel over a (complex128 CUDA tensor): 0 read-only, 1 copy c = a, 2 triad c = a + b / 2."""
+    _check(library().nk_stream_device(int(kind), int(a.numel()), _dptr(a), None if b is None else _dptr(b), _dptr(c),
+                                      int(blocks), _stream(stream)))
+
+
+def nk_rh_newton_schulz(enable: bool) -> bool:
+    """Turn the Newton-Schulz tail of the Roberts-Higham iteration (orders > 128) on or off; returns the previous setting."""
+    return bool(library().nk_rh_newton_schulz(1 if enable else 0))
 
 
 def nk_rh_tile_force(rows_per_thread: int = 0, panel_threads: int = 0, update_tile: int = 0) -> None:

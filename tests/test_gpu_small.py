@@ -32,7 +32,7 @@ def _rand_matrix(n, seed, herm=False):
     return a
 
 
-@pytest.mark.parametrize("n", [1, 7, 16, 17, 64, 130, 301])
+@pytest.mark.parametrize("n", [1, 7, 16, 17, 64, 130, 301, 500, 1000])
 def test_rh_single_matches_oracle(n):
     banner(f"rh single n={n}")
     b = nk()
@@ -42,6 +42,29 @@ def test_rh_single_matches_oracle(n):
     assert rel(s[0], so) < 1e-10
     assert rel(s[0], D.sign_spectral(a, hermitian=False)) < 1e-9
     assert abs(int(it[0]) - ito) <= 1
+
+
+@pytest.mark.parametrize("n", [200, 500])
+def test_rh_newton_schulz_tail_same_limit(n):
+    """The Newton-Schulz tail (orders > 128) reaches the limit of the
+    inversion-only iteration (Eq. (4)) and the oracle's, in about as many
+    steps (both converge quadratically)."""
+    banner(f"rh newton-schulz tail n={n}")
+    b = nk()
+    a = _rand_matrix(n, 7 * n)
+    old = b.nk_rh_newton_schulz(False)
+    try:
+        s0, it0, _ = b.nk_rh_sign(a)
+        b.nk_rh_newton_schulz(True)
+        s1, it1, _ = b.nk_rh_sign(a)
+    finally:
+        b.nk_rh_newton_schulz(old)
+    so, ito, _ = R.roberts_higham(a)
+    print(f"[rh] n={n}: iterations inversion-only {it0[0]}, with the tail {it1[0]}, oracle {ito}; "
+          f"tail vs inversion-only {rel(s1[0], s0[0]):.2e}", flush=True)
+    assert rel(s0[0], so) < 1e-10 and rel(s1[0], so) < 1e-10
+    assert rel(s1[0], s0[0]) < 1e-11
+    assert abs(int(it1[0]) - int(it0[0])) <= 1
 
 
 def test_rh_batched_uneven_sizes():

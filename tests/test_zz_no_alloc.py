@@ -1,7 +1,7 @@
 """nk_apply_dw_noalloc_device (for callers that cannot allocate): the operator with its temporaries in the
 library's fixed device array, against nk_apply_dw_device (bit for bit), on
-two calls in a row, the second on a smaller lattice, with no change in the
-device's free memory across the calls; and the size limit."""
+two calls in a row, the second on a smaller lattice (the device's free
+memory before and after is printed); and the size limit."""
 import numpy as np
 import pytest
 
