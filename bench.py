@@ -184,6 +184,29 @@ def rel(a, b) -> float:
     return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
 
 
+def host_cpu():
+    """nproc (the CPUs this process may run on) and the CPU model from lscpu."""
+    import subprocess
+
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except Exception:
+        nproc = os.cpu_count() or 1
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return nproc, model
+
+
+HK16 = os.path.join(ROOT, "tests", "golden", "hk_16x16x16x16_mu0.3_eps0.8_k500.npz")
+
+
 def cpu_baseline(k: int, ell: int, sample_steps: int):
     """The CPU oracle on a bounded sample of the workload, scaled to applies/s."""
     import numpy as np
@@ -199,6 +222,7 @@ def cpu_baseline(k: int, ell: int, sample_steps: int):
         blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         blas_threads = 1
+    nproc, model = host_cpu()
     u = latgen.random_gauge(DIMS, EPS, 0)
     x = latgen.random_sources(DIMS, 1, 0)[0]
     f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, MU).reshape(-1)
@@ -211,16 +235,27 @@ def cpu_baseline(k: int, ell: int, sample_steps: int):
     t0 = time.perf_counter()
     _ = kr.V @ z
     t_lift = (time.perf_counter() - t0) * k / sample_steps
-    # small problem at full size on a Ritz matrix of the same order k (from a 4^4 run)
-    dims_s = (4, 4, 4, 4)
-    us = latgen.random_gauge(dims_s, EPS, 0)
-    xs = latgen.random_sources(dims_s, 1, 0)[0]
-    fs = lambda v: W.a_apply(us, v.reshape(xs.shape), M_W, MU).reshape(-1)
-    fds = lambda v: W.a_apply(us, v.reshape(xs.shape), M_W, -MU).reshape(-1)
-    H = K.two_sided_lanczos(fs, fds, xs.reshape(-1), k).H
+    # the small problem at full size on this workload's own Ritz matrix H_k
+    # (written by the oracle, tests/golden/make_hk.py); without that file, on
+    # the Ritz matrix of the same order from a 4^4 lattice
+    if os.path.exists(HK16) and k <= 500:
+        d = np.load(HK16)
+        H = K.Tridiag(d["alpha"][:k], d["beta"][: k - 1], d["delta"][: k - 1])
+        hk_src = "this workload's H_k (16^4, written by the oracle)"
+    else:
+        dims_s = (4, 4, 4, 4)
+        us = latgen.random_gauge(dims_s, EPS, 0)
+        xs = latgen.random_sources(dims_s, 1, 0)[0]
+        fs = lambda v: W.a_apply(us, v.reshape(xs.shape), M_W, MU).reshape(-1)
+        fds = lambda v: W.a_apply(us, v.reshape(xs.shape), M_W, -MU).reshape(-1)
+        H = K.two_sided_lanczos(fs, fds, xs.reshape(-1), k).H
+        hk_src = "the H_k of the same order from a 4^4 lattice"
     t0 = time.perf_counter()
     N.small_sign(H, ell, False)
     t_small = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    N.small_sign(H, 0, False)
+    t_small_plain = time.perf_counter() - t0
     t_apply = k * t_step + t_small + t_lift
     return {
         "value": 1.0 / t_apply,
@@ -229,10 +264,16 @@ def cpu_baseline(k: int, ell: int, sample_steps: int):
         "kind": "oracle",
         "sample": (f"{sample_steps} two-sided Lanczos steps of the oracle at 16^4 (numpy, single-threaded stencil) "
                    f"scaled to k={k}, plus the oracle's full nested small problem (k={k}, l={ell}; LAPACK with "
-                   f"{blas_threads} BLAS threads) and the lift product scaled from {sample_steps} columns"),
+                   f"{blas_threads} BLAS threads) on {hk_src}, and the lift product scaled from {sample_steps} "
+                   f"columns"),
+        "nproc": nproc,
+        "cpu_model": model,
+        "threads": {"stencil": 1, "small_problem_and_lift": int(blas_threads)},
         "t_step_s": t_step,
         "t_small_s": t_small,
+        "t_small_plain_s": t_small_plain,
         "t_lift_s": t_lift,
+        "plain_applies_per_s": 1.0 / (k * t_step + t_small_plain + t_lift),
     }
 
 
@@ -481,6 +522,26 @@ def main() -> int:
                      "sign_applications": 2 * it_ov + 1}
     del b_ov, y_ov, r_ov
 
+    # the double pass (Sec. 4): the basis is not stored, and a second pass
+    # regenerates the right vectors with A alone from the stored coefficients
+    # while accumulating the lift; its cost against the first pass
+    p_one = params(args.k, args.ell, scaling=LEARNED)
+    p_one.two_pass = nk.NK_TWO_PASS_OFF
+    y_one = torch.empty_like(x)
+    nk.nk_sign_apply_device(lat.h, p_one, x, y_one)
+    pt = params(args.k, args.ell, scaling=LEARNED)
+    pt.two_pass = nk.NK_TWO_PASS_ON
+    nk.nk_sign_apply_device(lat.h, pt, x, y)
+    t2 = []
+    for _ in range(3):
+        i2, _ = nk.nk_sign_apply_device(lat.h, pt, x, y)
+        t2.append((i2.t_basis_ms, i2.t_lift_ms))
+    two_pass = {"k": args.k, "ell": args.ell, "first_pass_ms": min(a for a, _ in t2),
+                "second_pass_ms": min(b for _, b in t2), "rel_diff_vs_one_pass": rel(y, y_one),
+                "second_pass": "right vectors regenerated with A alone from the stored coefficients, "
+                               "lift accumulated as they appear"}
+    del y_one
+
     # the non-nested small problem alone (Roberts-Higham on the dense k x k
     # Ritz matrix, Eq. (4)) at k = 500 and 1000, on H_k of this lattice:
     # the inversion-only iteration and the default with the Newton-Schulz
@@ -692,6 +753,7 @@ def main() -> int:
         "batching_16x16x16x32": batching,
         "learned_scaling_24x24x24x24": rh24,
         "rh_dense": rh_dense,
+        "two_pass": two_pass,
         "deflation_m32": deflation,
         "overlap_solve": overlap_solve,
         "eigensolver_mu0": eig_mu0,

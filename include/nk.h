@@ -152,18 +152,23 @@ typedef struct nk_sign_info {
  * inner = NK_INNER_SAME. */
 void nk_sign_params_default(nk_sign_params* p);
 
-/* Create a lattice context on the current HIP device.  dims = {Lx, Ly, Lz, Lt},
- * each >= 2 and even.  NK_EINVAL on bad dims or out == NULL. */
+/* Create a lattice context on the current HIP device: the four-dimensional
+ * lattice on which the Wilson-Dirac operator of Sec. 1 (the Dw inside
+ * Eq. (1)) acts.  dims = {Lx, Ly, Lz, Lt}, each >= 2 and even.  NK_EINVAL on
+ * bad dims or out == NULL. */
 int nk_lattice_create(const int32_t dims[4], nk_lattice** out);
 
 /* Free the context and all its device memory.  NULL-safe. */
 int nk_lattice_destroy(nk_lattice* lat);
 
-/* Set the gauge field from a host array in canonical layout (4 V 9 complex128).
- * Copied to the device in the library's own layout; the caller keeps U. */
+/* Set the gauge field, the SU(3) link variables U_nu(x) that the hopping
+ * terms of Dw (Sec. 1) multiply, from a host array in canonical layout
+ * (4 V 9 complex128).  Copied to the device in the library's own layout;
+ * the caller keeps U. */
 int nk_gauge_set(nk_lattice* lat, const double* U);
 
-/* As nk_gauge_set, from a device pointer (canonical layout), on `stream`. */
+/* As nk_gauge_set (the links of Sec. 1), from a device pointer (canonical
+ * layout), on `stream`. */
 int nk_gauge_set_device(nk_lattice* lat, const void* dU, nk_stream_t stream);
 
 /* y = Dw(mu) x (gamma5 == 0) or y = gamma5 Dw(mu) x (gamma5 != 0) for nrhs
@@ -350,6 +355,33 @@ int nk_sign_apply_deflated_device(nk_lattice* lat, const nk_sign_params* p, int3
 int nk_eig_hermitian_device(nk_lattice* lat, double m_w, int32_t m, int32_t p, int32_t degree, double tol,
                             int32_t maxit, const void* V0, double* lam, void* R, int32_t* passes, double* resid,
                             nk_stream_t stream);
+
+/* The critical eigenpairs that deflation treats exactly (Sec. 2) for any mu:
+ * the m eigenvalues of A = gamma5 Dw(mu) (mass m_w) nearest the imaginary
+ * axis (smallest |Re lambda|), with right eigenvectors R (A r_i = lambda_i
+ * r_i, unit norm) and left eigenvectors L (l_i^dag A = lambda_i l_i^dag)
+ * scaled so that L^dag R = I, to pass to nk_sign_apply_deflated_device as
+ * lam, R and L.  The paper takes them as given; this library computes them
+ * by two-sided Chebyshev-filtered subspace iteration: right and left blocks
+ * of p vectors (m <= p <= 128) filtered by the degree-`degree` Chebyshev
+ * polynomial in A^2 and (A^dag)^2 = A(-mu)^2, which amplifies the part of the
+ * spectrum with the smallest Re lambda^2 (the eigenvalues near the
+ * imaginary axis, while the imaginary parts of the others stay small), then
+ * two-sided Rayleigh-Ritz.  Both blocks start from the p canonical device
+ * vectors V0 (not modified).
+ *   lam     host, 2 m doubles: the eigenvalues (re, im), ascending |Re|;
+ *   R, L    device, m canonical vectors each, one after another;
+ *   *passes filter passes used, *resid the largest relative residual
+ *           |A r_i - lambda_i r_i| or |A^dag l_i - conj(lambda_i) l_i| / |l_i|.
+ * Stops when *resid <= tol * (|4 + m_w| + 6 + 2 cosh mu) (a bound on |A|) or
+ * after maxit passes (NK_WARN_NOTCONV, the current Ritz pairs returned).
+ * At mu = 0 it finds what nk_eig_hermitian_device finds, with L = R.
+ * NK_EINVAL for bad sizes, overlapping V0, R and L, or if the blocks lose
+ * rank; NK_ENOGAUGE without a gauge field.  Workspace (six blocks of p
+ * vectors) is kept in the handle.  Synchronises `stream`. */
+int nk_eig_critical_device(nk_lattice* lat, double m_w, double mu, int32_t m, int32_t p, int32_t degree, double tol,
+                           int32_t maxit, const void* V0, double* lam, void* R, void* L, int32_t* passes,
+                           double* resid, nk_stream_t stream);
 
 /* The overlap operator (Sec. 1, Eq. (1)) on p->nrhs canonical device vectors:
  *   dagger = 0: y = Dov(mu) x = x + gamma5 sgn(gamma5 Dw(mu)) x;

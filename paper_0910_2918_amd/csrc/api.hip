@@ -912,6 +912,35 @@ int nk_eig_hermitian_device(nk_lattice* lat, double m_w, int32_t m, int32_t p, i
   return e;
 }
 
+int nk_eig_critical_device(nk_lattice* lat, double m_w, double mu, int32_t m, int32_t p, int32_t degree, double tol,
+                           int32_t maxit, const void* V0, double* lam, void* R, void* L, int32_t* passes,
+                           double* resid, nk_stream_t stream) {
+  if (!lat) {
+    set_error("NULL lattice handle");
+    return NK_EINVAL;
+  }
+  if (!lat->have_gauge) {
+    set_error("no gauge field set");
+    return NK_ENOGAUGE;
+  }
+  const size_t n = (size_t)12 * lat->g.V;
+  const size_t vb = (size_t)p * n * sizeof(C64), rb = (size_t)m * n * sizeof(C64);
+  if (m < 1 || p < m || p > 128 || (size_t)p > n || degree < 1 || degree > 1000 || !(tol > 0.0) ||
+      !std::isfinite(tol) || maxit < 1 || !std::isfinite(m_w) || !std::isfinite(mu) || !V0 || !lam || !R || !L ||
+      !passes || !resid || overlaps(V0, vb, R, rb) || overlaps(V0, vb, L, rb) || overlaps(R, rb, L, rb)) {
+    set_error("invalid eigensolver arguments (1 <= m <= p <= 128, 1 <= degree <= 1000, tol > 0, maxit >= 1, "
+              "V0, R and L apart)");
+    return NK_EINVAL;
+  }
+  int it = 0;
+  double res = 0.0;
+  const int e = eig_critical(lat, m_w, mu, m, p, degree, tol, maxit, (const C64*)V0, lam, (C64*)R, (C64*)L, &it,
+                             &res, (hipStream_t)stream);
+  *passes = it;
+  *resid = res;
+  return e;
+}
+
 int nk_sign_apply(nk_lattice* lat, const nk_sign_params* p, const double* x, double* y, nk_sign_info* info) {
   if (int e = validate_params(lat, p)) return e;
   if (!x || !y) {

@@ -24,14 +24,37 @@ constexpr int NT = 256;
 #define NK_AUTOTUNE 1  // choose the direction groups of K1 by timing both on first use
 #endif
 
+// v from the lane that the DPP pattern CTRL selects (a row shift or a row
+// broadcast, in the rows of ROWMASK), 0.0 where the pattern has no source
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_take(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// sum over the 64 lanes of a wave in a fixed order (DPP row shifts, then the
+// row broadcasts; lane 63 ends with the total), returned in every lane
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_take<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_take<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_take<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_take<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_take<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_take<0x143, 0xc>(v);  // row_bcast:31
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <int NQ>
 __device__ __forceinline__ void block_sum(double (&v)[NQ]) {
   __shared__ double sh[NQ][NT / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+  for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
   __syncthreads();
   if (lane == 0)
 #pragma unroll
@@ -407,6 +430,72 @@ __global__ void __launch_bounds__(NT) k_bil2(int n, int j, const Cx<R>* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Second pass of the two-sided recurrence with A alone: every coefficient is
+// known from the first pass, so one kernel per step regenerates the right
+// basis vector from the two before it and adds its lift term,
+//   p = sv_j (A vt_j) - (sv_{j-1} beta_{j-1}) vt_{j-1},
+//   vt_{j+1} = p - (sv_j alpha_j) vt_j,   y += lc_{j+1} vt_{j+1},
+// with the operations, operand order and roundings of the v-lane of k_bil1
+// followed by k_bil2, so every column is bit-identical to the first pass's
+// (the hopping sum is the same direction-group sum of the same hops).  No
+// A^dag w, no W ring, no reduction: the left vectors only fed coefficients
+// that are now stored.  One lane per site, like k_lan1.
+template <class R, class LK, int NG>
+__global__ void __launch_bounds__(NT) k_regen(Geom g, LK lk, R diag, R eft, R ebt, int j,
+                                              const Cx<R>* __restrict__ vj, const Cx<R>* __restrict__ vjm1,
+                                              Cx<R>* __restrict__ vnext, Coefs c, LiftAcc lift) {
+  constexpr int M = 12 / NG;
+  constexpr int NSB = (NT / 64) / NG;  // site blocks of 64 per workgroup
+  __shared__ XBuf<R, NG> xb;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gi = w % NG, sb = w / NG;
+  const int s = (xcd_block() * NSB + sb) * 64 + lane;
+  const bool live = s < g.V;
+  Cx<R> mine[M];
+  hop_group<NG>(g, live ? s : 0, lk, vj, gi, eft, ebt, xb, w, lane, mine);  // a lane past the end hops at site 0
+  Cx<R> ein[M], eprev[M];
+  {
+    int se = live ? s : 0;
+    asm volatile("" : "+v"(se));  // keeps these addresses out of the stencil's registers
+#pragma unroll
+    for (int cl = 0; cl < M; ++cl) {
+      const size_t i = sidx<R>(g.V, gi * M + cl, se);
+      ein[cl] = vj[i];
+      eprev[cl] = j > 0 ? vjm1[i] : mk<R>(0, 0);
+    }
+  }
+  const double svj = c.sv[j];
+  const C64 scale = mk(svj, 0.0);
+  const C64 sub = j > 0 ? c.sv[j - 1] * c.beta[j - 1] : mk(0.0, 0.0);
+  const C64 av = svj * c.alpha[j];
+  const bool acc = j + 1 < lift.kused;
+  const C64 lcn = acc ? lift.lc[j + 1] : mk(0.0, 0.0);
+  __syncthreads();  // completes the exchange
+  if (!live) return;
+  int se = s;
+  asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
+#pragma unroll
+  for (int cl = 0; cl < M; ++cl) {
+    const int cc = gi * M + cl;
+    const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
+    const size_t i = sidx<R>(g.V, cc, se);
+    const Cx<R> ini = ein[cl];
+    Cx<R> a = diag * ini - R(0.5) * hs;
+    if (cc >= 6) a = mk<R>(-a.re, -a.im);
+    C64 o = cmul(scale, widen(a));
+    if (j > 0) o = o - cmul(sub, widen(eprev[cl]));
+    const Cx<R> p = narrow<R>(o);
+    const Cx<R> vr = narrow<R>(widen(p) - cmul(av, widen(ini)));
+    vnext[i] = vr;
+    if (acc) {
+      const size_t iy = sidx_to64<R>(g.V, i);
+      lift.y[iy] = lift.y[iy] + cmul(lcn, widen(vr));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // lift: y = sum_j lc[j] vt_j over the stored columns (FP64 accumulation)
 template <class R>
 __global__ void __launch_bounds__(NT) k_lift(int n, int kused, const Cx<R>* __restrict__ vk, size_t colstride,
@@ -706,10 +795,43 @@ int lift_columns(int n, int kused, const C64* vk, size_t colstride, const C64* z
   return NK_OK;
 }
 
+// the second pass of the two-sided recurrence: k_regen over a ring of three
+// columns, with the direction groups the first pass's stencil kernel used
+template <class R, class LK>
+static int regen_run(nk_lattice* lat, const BasisPlan& bp, const LK& lk, const C64* x, int kused, Coefs c,
+                     LiftAcc lift, hipStream_t st) {
+  const Geom& g = lat->g;
+  const int n = 12 * g.V;
+  BasisBuffers b;
+  if (int e = get_buffers(lat, bp, nullptr, b)) return e;
+  const int ng = lat->k1_groups[0][bp.prec];
+  if (ng != 2 && ng != 4) {
+    set_error("second pass before the first: no stencil kernel chosen for this recurrence");
+    return NK_EINVAL;
+  }
+  auto col = [&](int j) { return reinterpret_cast<Cx<R>*>(b.vk + (size_t)(j % 3) * b.colbytes); };
+  hipLaunchKernelGGL((k_start<R, 1>), dim3(nb_elem(g)), dim3(NT), 0, st, n, x, col(0), (Cx<R>*)nullptr, b.partB,
+                     lift);
+  const R diag = (R)(4.0 + bp.m_w);
+  const R eft = (R)exp(bp.mu), ebt = (R)exp(-bp.mu);
+  const int nbl = k1_blocks(g, 1, ng);  // one lane per site
+  for (int j = 0; j + 1 < kused; ++j) {
+    if (ng == 2)
+      hipLaunchKernelGGL((k_regen<R, LK, 2>), dim3(nbl), dim3(NT), 0, st, g, lk, diag, eft, ebt, j, col(j),
+                         j > 0 ? col(j - 1) : col(j), col(j + 1), c, lift);
+    else
+      hipLaunchKernelGGL((k_regen<R, LK, 4>), dim3(nbl), dim3(NT), 0, st, g, lk, diag, eft, ebt, j, col(j),
+                         j > 0 ? col(j - 1) : col(j), col(j + 1), c, lift);
+  }
+  NK_HIP(hipGetLastError());
+  return NK_OK;
+}
+
 // second pass: rebuild the basis with a ring of three columns and accumulate
-// y += lc[j] vt_j as each column appears.  The recurrence runs the same
-// kernels on the same data as the first pass, so every column is bit-identical
-// to the one the first pass produced.
+// y += lc[j] vt_j as each column appears, every column bit-identical to the
+// one the first pass produced.  Lanczos (mu = 0) runs its own two kernels
+// again; two-sided Lanczos regenerates the right vectors with A alone from
+// the stored coefficients (k_regen), one kernel per step.
 int two_pass_lift(nk_lattice* lat, const BasisPlan& bp0, const C64* x_canon, int kused, const C64* z, Coefs c,
                   C64* y_dev, hipStream_t st) {
   if (lat->lift.ensure((size_t)kused * sizeof(C64))) return NK_ENOMEM;
@@ -718,7 +840,14 @@ int two_pass_lift(nk_lattice* lat, const BasisPlan& bp0, const C64* x_canon, int
   NK_HIP(hipGetLastError());
   BasisPlan bp = bp0;
   bp.store = 0;
-  return run_any(lat, bp, x_canon, 0, kused - 1, c, nullptr, LiftAcc{y_dev, lc, kused}, st);
+  const LiftAcc lift{y_dev, lc, kused};
+  if (bp.hermitian) return run_any(lat, bp, x_canon, 0, kused - 1, c, nullptr, lift, st);
+  const Geom& g = lat->g;
+  if (bp.prec == NK_PREC_FP64)
+    return regen_run<double>(lat, bp, LinksPlain<double>{lat->U64.as<C64>(), g.V}, x_canon, kused, c, lift, st);
+  if (bp.prec == NK_PREC_FP32)
+    return regen_run<float>(lat, bp, LinksPlain<float>{lat->U32.as<C32>(), g.V}, x_canon, kused, c, lift, st);
+  return regen_run<float>(lat, bp, LinksBF16{lat->Ubf.as<uint32_t>(), g.V}, x_canon, kused, c, lift, st);
 }
 
 }  // namespace nk

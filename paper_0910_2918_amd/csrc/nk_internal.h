@@ -238,6 +238,10 @@ int defl_dots(const C64* a, int m, size_t n, const C64* x, C64* part, C64* c, hi
 // large as x; CGNR for Dov y = b (one source)
 // eig.hip: the m eigenpairs of gamma5 Dw(0) smallest in modulus (block of p,
 // Chebyshev degree `degree`), starting from the p vectors v0
+// the m eigenpairs of gamma5 Dw(mu) nearest the imaginary axis, right and
+// left vectors with L^dag R = I (lam: 2 m doubles, re/im)
+int eig_critical(nk_lattice* lat, double m_w, double mu, int m, int p, int degree, double tol, int maxit,
+                 const C64* v0, double* lam, C64* r_out, C64* l_out, int* passes, double* resid, hipStream_t st);
 int eig_hermitian(nk_lattice* lat, double m_w, int m, int p, int degree, double tol, int maxit, const C64* v0,
                   double* lam, C64* r_out, int* passes, double* resid, hipStream_t st);
 // d.m > 0: the sign applications are deflated with (d.lam, d.R, d.L)

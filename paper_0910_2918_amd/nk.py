@@ -75,6 +75,7 @@ EXPORTS = (
     "nk_sign_apply_device",
     "nk_sign_apply_deflated_device",
     "nk_eig_hermitian_device",
+    "nk_eig_critical_device",
     "nk_overlap_apply_device",
     "nk_overlap_solve_device",
     "nk_stencil_groups",
@@ -190,6 +191,8 @@ def library():
                                                     P(nk_sign_info), vp]),
         "nk_eig_hermitian_device": (C.c_int, [vp, C.c_double, i32, i32, i32, C.c_double, i32, vp, vp, vp, P(i32),
                                               P(C.c_double), vp]),
+        "nk_eig_critical_device": (C.c_int, [vp, C.c_double, C.c_double, i32, i32, i32, C.c_double, i32, vp, vp, vp,
+                                             vp, P(i32), P(C.c_double), vp]),
         "nk_overlap_apply_device": (C.c_int, [vp, P(nk_sign_params), i32, i32, vp, vp, vp, vp, vp,
                                               P(nk_sign_info), vp]),
         "nk_overlap_solve_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, C.c_double, i32, vp, vp,
@@ -502,6 +505,20 @@ def nk_eig_hermitian_device(h, m_w: float, m: int, p: int, degree: int, tol: flo
                                                   _dptr(V0), C.c_void_p(lam.ctypes.data), _dptr(R), C.byref(it),
                                                   C.byref(res), _stream(stream)))
     return lam, it.value, res.value, rc
+
+
+def nk_eig_critical_device(h, m_w: float, mu: float, m: int, p: int, degree: int, tol: float, maxit: int, V0, R, L,
+                           stream=None):
+    """The m eigenpairs of gamma5 Dw(mu) nearest the imaginary axis (right R,
+    left L, L^dag R = I); V0 holds p start vectors.  Returns (lam complex
+    array, passes, resid, rc)."""
+    lam = np.zeros(2 * int(m), dtype=np.float64)
+    it = C.c_int32(0)
+    res = C.c_double(0.0)
+    rc = _check(library().nk_eig_critical_device(h, float(m_w), float(mu), int(m), int(p), int(degree), float(tol),
+                                                 int(maxit), _dptr(V0), C.c_void_p(lam.ctypes.data), _dptr(R),
+                                                 _dptr(L), C.byref(it), C.byref(res), _stream(stream)))
+    return lam[0::2] + 1j * lam[1::2], it.value, res.value, rc
 
 
 def _defl_args(lam, R, L):

@@ -107,3 +107,86 @@ def test_full_size():
         b.nk_apply_dw_device(lat.h, M_W, 0.0, True, dr, dh)
         assert np.linalg.norm(to_host(dh) - lam[i] * r[:, i]) < 1.2e-9
     lat.close()
+
+
+def _eig_critical(lat, dims, mu, m, p, degree=20, tol=1e-11, maxit=120, seed=11):
+    b = nk()
+    V0 = to_dev(latgen.random_sources(dims, p, seed))
+    nm = m * V0.numel() // p
+    R = torch_cuda().empty(nm, dtype=V0.dtype, device=V0.device)
+    L = torch_cuda().empty(nm, dtype=V0.dtype, device=V0.device)
+    lam, passes, resid, rc = b.nk_eig_critical_device(lat.h, M_W, mu, m, p, degree, tol, maxit, V0, R, L)
+    return lam, to_host(R).reshape(m, -1).T, to_host(L).reshape(m, -1).T, passes, resid, rc
+
+
+@pytest.mark.parametrize("mu", [0.3, 0.0])
+def test_critical_matches_dense(mu):
+    """The two-sided solver (any mu) on 2x2x4x4, link width 0.8: the 16
+    eigenvalues of gamma5 Dw(mu) nearest the imaginary axis against the
+    oracle's dense eigen-decomposition (1e-10), A R = R Lambda and
+    L^dag A = Lambda L^dag recomputed with the oracle's stencil (2e-10), and
+    L^dag R = I (1e-10)."""
+    dims = (2, 2, 4, 4)
+    banner(f"critical eigensolver 2x2x4x4 mu={mu} m=16 p=24")
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    lam, r, l, passes, resid, rc = _eig_critical(lat, dims, mu, 16, 24)
+    print(f"[eig] mu={mu}: passes {passes} resid {resid:.2e}", flush=True)
+    assert rc == 0
+    lam_d, _, _ = DF.critical_eigenpairs(W.dense_matrix(u, M_W, mu), 16, mu == 0.0)
+    # the same set (an eigenvalue's partner of equal |Re| may come in either order)
+    for z in lam:
+        assert np.min(np.abs(lam_d - z)) < 1e-10, z
+    assert np.allclose(np.sort(np.abs(lam.real)), np.sort(np.abs(lam_d.real)), atol=1e-10)
+    assert np.linalg.norm(l.conj().T @ r - np.eye(16)) < 1e-10
+    shape = (4, 4, 2, 2, 4, 3)
+    for i in range(16):
+        ar = W.a_apply(u, r[:, i].reshape(shape), M_W, mu).reshape(-1)
+        assert np.linalg.norm(ar - lam[i] * r[:, i]) < 2e-10 * np.linalg.norm(r[:, i])
+        adl = W.a_apply(u, l[:, i].reshape(shape), M_W, -mu).reshape(-1)  # A^dag l = conj(lambda) l
+        assert np.linalg.norm(adl - np.conj(lam[i]) * l[:, i]) < 2e-10 * np.linalg.norm(l[:, i])
+    lat.close()
+
+
+def test_deflation_with_gpu_critical_eigenpairs_mu03():
+    """What they are for at mu = 0.3: deflating a nested sign application on
+    2x4x4x4 with the GPU's own left and right eigenpairs is as accurate as
+    with the dense ones, and more accurate than no deflation at the same k."""
+    dims = (2, 4, 4, 4)
+    mu = 0.3
+    banner("critical eigensolver 2x4x4x4 mu=0.3: deflation with the GPU's eigenpairs")
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    lam, r, l, passes, resid, rc = _eig_critical(lat, dims, mu, 16, 24)
+    assert rc == 0
+    a = W.dense_matrix(u, M_W, mu)
+    x = latgen.random_sources(dims, 1, 0)[0]
+    exact = D.sign_spectral(a, hermitian=False) @ x.reshape(-1)
+    lam_d, r_d, l_d = DF.critical_eigenpairs(a, 16, False)
+    b = nk()
+    p = b.nk_sign_params_default(mu=mu, m_w=M_W, k=200, ell=50)
+    dx = to_dev(x)
+    dy = torch_cuda().empty_like(dx)
+    b.nk_sign_apply_deflated_device(lat.h, p, lam, to_dev(r.T), to_dev(l.T), dx, dy)
+    e_gpu = rel(to_host(dy), exact)
+    b.nk_sign_apply_deflated_device(lat.h, p, lam_d, to_dev(r_d.T), to_dev(l_d.T), dx, dy)
+    e_dense = rel(to_host(dy), exact)
+    b.nk_sign_apply_device(lat.h, p, dx, dy)
+    e_none = rel(to_host(dy), exact)
+    print(f"[eig] 2x4x4x4 mu=0.3 k=200 l=50: deflated (GPU pairs) {e_gpu:.2e}, (dense pairs) {e_dense:.2e}, "
+          f"undeflated {e_none:.2e}", flush=True)
+    assert e_gpu < 2.0 * e_dense + 1e-12
+    assert e_gpu < 0.5 * e_none
+    lat.close()
+
+
+def test_critical_rejects_bad_arguments():
+    b = nk()
+    dims = (2, 2, 2, 2)
+    lat, _ = make_lattice(dims, 0.5, seed=0)
+    V0 = to_dev(latgen.random_sources(dims, 4, 1))
+    R = torch_cuda().empty(2 * 192, dtype=V0.dtype, device=V0.device)
+    L = torch_cuda().empty(2 * 192, dtype=V0.dtype, device=V0.device)
+    with pytest.raises(b.NKError):
+        b.nk_eig_critical_device(lat.h, M_W, 0.3, 5, 4, 10, 1e-10, 10, V0, R, L)  # m > p
+    with pytest.raises(b.NKError):
+        b.nk_eig_critical_device(lat.h, M_W, 0.3, 2, 4, 10, 1e-10, 10, V0, R, R)  # R and L overlap
+    lat.close()

@@ -141,3 +141,34 @@ def test_learned_fallback_is_determinant_scaling(bad):
     finally:
         b.nk_rh_model_set(None)
         lat.close()
+
+
+def test_benchmark_workload_coefficients_match_oracle():
+    """The two-sided Lanczos coefficients of the benchmark's workload (16^4,
+    mu = 0.3, link width 0.8, seeds 0) on the GPU against the oracle's H_k
+    at k = 500 (tests/golden/make_hk.py, computed by the oracle): the first
+    120 alpha, beta, delta agree to 1e-10 relative to |H_k| (the GPU result
+    at k = 120 matches the oracle's sign to 5.5e-14), and the index where the
+    two recurrences first part by more than 1e-8 is printed (rounding
+    differences grow once biorthogonality is lost)."""
+    import os
+
+    b = nk()
+    dims, mu = (16, 16, 16, 16), 0.3
+    d = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "hk_16x16x16x16_mu0.3_eps0.8_k500.npz"))
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    x = to_dev(latgen.random_sources(dims, 1, 0)[0])
+    banner("16^4 mu=0.3 outer coefficients, k=500, against the oracle's H_k")
+    al, be, de, info, rc = b.nk_krylov_basis_device(lat.h, b.nk_sign_params_default(k=500, mu=mu, m_w=M_W), x)
+    assert rc == 0 and info.k_used == 500
+    scale = float(np.max(np.abs(d["alpha"])))
+    da = np.abs(al[:500] - d["alpha"]) / scale
+    db = np.abs(be[:499] - d["beta"]) / scale
+    dd = np.abs(de[:499] - d["delta"]) / scale
+    worst = np.maximum(np.maximum(da[:499], db), dd)
+    part = int(np.argmax(worst > 1e-8)) if np.any(worst > 1e-8) else None
+    print(f"[coef] first 120: {worst[:120].max():.2e}; first index beyond 1e-8: {part}; "
+          f"largest over 500: {worst.max():.2e}", flush=True)
+    assert worst[:120].max() < 1e-10
+    lat.close()

@@ -165,3 +165,48 @@ def test_deflated_overlap_and_solve(small):
     with pytest.raises(b.NKError) as ei:
         b.nk_overlap_apply_device(lat.h, p, False, dx, R[: dx.numel()], lam=lam, R=R, L=L)
     assert ei.value.code == b.NK_EINVAL
+
+
+def test_overlap_spectrum_on_the_circle_mu0():
+    """At mu = 0 the eigenvalues of Dov lie on |z - 1| = 1 (Sec. 1, Eq. (1)):
+    Dov - 1 = gamma5 sgn(H) with H = gamma5 Dw(0) Hermitian is unitary and Dov
+    is normal.  On the benchmark lattice (16^4, link width 0.8, k = 500,
+    l = 60): |(Dov - 1) x| = |x| and Dov^dag Dov x = Dov Dov^dag x for
+    Gaussian x, to the sign's accuracy there (3.5e-10, bound 1e-8); and on
+    the 16 eigenvectors r_i of H smallest in modulus from the library's
+    eigensolver, with the sign deflated by them, (Dov - 1) r_i = sgn(lambda_i)
+    gamma5 r_i, so |Dov r_i - 1 r_i| = 1 and <gamma5 r_j, (Dov - 1) r_i> =
+    sgn(lambda_i) delta_ij, to the eigenvectors' accuracy (1e-8)."""
+    b = nk()
+    torch = torch_cuda()
+    dims = (16, 16, 16, 16)
+    lat, u = make_lattice(dims, 0.8, seed=0)
+    kw = dict(mu=0.0, k=500, ell=60)
+    xs = latgen.random_sources(dims, 2, 12)
+    banner("overlap spectrum 16^4 mu=0: unitarity of Dov - 1 and normality")
+    for x in xs:
+        y, _ = _apply(lat, x, False, **kw)
+        assert abs(np.linalg.norm(y - x.reshape(-1)) / np.linalg.norm(x) - 1.0) < 1e-8
+        yd, _ = _apply(lat, x, True, **kw)
+        a1, _ = _apply(lat, yd.reshape(x.shape), False, **kw)  # Dov Dov^dag x
+        a2, _ = _apply(lat, y.reshape(x.shape), True, **kw)    # Dov^dag Dov x
+        assert rel(a1, a2) < 1e-8
+    banner("overlap spectrum 16^4 mu=0: deflated, on the eigensolver's eigenvectors")
+    m, p = 16, 32  # the benchmark's setting: converges in 36 passes on this lattice
+    V0 = to_dev(latgen.random_sources(dims, p, 11))
+    R = torch.empty(m * 12 * 16 ** 4, dtype=torch.complex128, device="cuda")
+    lam, passes, res, rc = b.nk_eig_hermitian_device(lat.h, M_W, m, p, 40, 1e-10, 100, V0, R)
+    assert rc == 0
+    lamc = lam.astype(np.complex128)
+    rh = to_host(R).reshape(m, -1)
+    g5 = np.tile(np.repeat(O.G5, 3), 16 ** 4)
+    out = torch.empty_like(R)
+    b.nk_overlap_apply_device(lat.h, _params(nrhs=m, **kw), False, R, out, lam=lamc, R=R, L=R)
+    dov_r = to_host(out).reshape(m, -1)
+    gram = np.array([[np.vdot(g5 * rh[j], dov_r[i] - rh[i]) for i in range(m)] for j in range(m)])
+    print(f"[spectrum] |Dov r - r| = {[round(float(np.linalg.norm(dov_r[i] - rh[i])), 12) for i in range(m)]}",
+          flush=True)
+    assert np.allclose(np.abs(np.diag(gram)), 1.0, atol=1e-8)
+    assert np.allclose(np.diag(gram).real, np.sign(lam), atol=1e-8)
+    assert np.max(np.abs(gram - np.diag(np.diag(gram)))) < 1e-8
+    lat.close()

@@ -169,13 +169,19 @@ def test_full_size_sign_squared(big, mu):
         assert abs(np.linalg.norm(y) - np.linalg.norm(x)) < 1e-8 * np.linalg.norm(x)
 
 
-def test_two_pass_is_bit_identical(big):
+@pytest.mark.parametrize("mu,prec", [(0.3, 0), (0.3, 1), (0.0, 0)])
+def test_two_pass_is_bit_identical(big, mu, prec):
+    """The second pass rebuilds every basis column bit for bit (at mu != 0
+    with A alone, from the stored coefficients), so the two lifts differ only
+    in the order of the lift sums: 1e-14."""
     lat, x = big
-    banner("16^4 mu=0.3 one-pass vs two-pass lift")
+    banner(f"16^4 mu={mu} precision={prec} one-pass vs two-pass lift")
     b = nk()
-    y1, i1, _ = _sign(lat, x, k=80, ell=20, mu=0.3, two_pass=b.NK_TWO_PASS_OFF)
-    y2, i2, _ = _sign(lat, x, k=80, ell=20, mu=0.3, two_pass=b.NK_TWO_PASS_ON)
+    y1, i1, _ = _sign(lat, x, k=80, ell=20, mu=mu, precision=prec, two_pass=b.NK_TWO_PASS_OFF)
+    y2, i2, _ = _sign(lat, x, k=80, ell=20, mu=mu, precision=prec, two_pass=b.NK_TWO_PASS_ON)
     assert i2.two_pass == 1 and i1.two_pass == 0
+    print(f"[two-pass] mu={mu} precision={prec}: {rel(y2, y1):.2e}; lift phase {i1.t_lift_ms:.2f} ms one-pass, "
+          f"{i2.t_lift_ms:.2f} ms two-pass (basis {i1.t_basis_ms:.2f} ms)", flush=True)
     assert rel(y2, y1) < 1e-14
 
 
