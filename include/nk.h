@@ -443,6 +443,17 @@ int nk_rh_tile_force(int32_t rows_per_thread, int32_t panel_threads, int32_t upd
 int nk_rh_newton_schulz(int32_t enable);
 int nk_rh_tile_choice(int32_t n, int32_t batch, int32_t shape[4]);
 
+/* Sources per workgroup (1, 2 or 4) of the lockstep stencil kernel
+ * (params.block > 0): with 2 or 4, the lanes of one site carry that many
+ * sources and share each link load.  The library times the three once per
+ * handle on the first lockstep run and keeps the fastest (a larger group only
+ * when more than 5% faster).  set = 1, 2 or 4 fixes the choice on this handle
+ * for later runs; set = 0 changes nothing.  Returns the choice before the
+ * call (0 before the first lockstep run); NK_EINVAL for a NULL handle or
+ * another set.  The group changes the order of the partial sums of w^dag A v,
+ * so results differ between group sizes by rounding. */
+int nk_block_group(nk_lattice* lat, int32_t set);
+
 /* Direction groups (2 or 4) of the outer-recurrence stencil kernel that the
  * autotuner chose on this handle for the given precision and recurrence
  * (hermitian != 0: Lanczos), 0 before the first basis run; NK_EINVAL for a

@@ -604,6 +604,16 @@ int nk_rh_model_set(const float* params) { return nk::mlp_model_set(params); }
 
 int nk_rh_newton_schulz(int32_t enable) { return nk::rh_newton_schulz(enable); }
 
+int nk_block_group(nk_lattice* lat, int32_t set) {
+  if (!lat || !(set == 0 || set == 1 || set == 2 || set == 4)) {
+    set_error("nk_block_group: a handle and set in {0, 1, 2, 4}");
+    return NK_EINVAL;
+  }
+  const int cur = lat->blk_group[1] ? lat->blk_group[1] : lat->blk_group[0];
+  if (set) lat->blk_group[0] = lat->blk_group[1] = set;
+  return cur;
+}
+
 int nk_rh_tile_force(int32_t rows_per_thread, int32_t panel_threads, int32_t update_tile) {
   return nk::rh_tile_force(rows_per_thread, panel_threads, update_tile);
 }

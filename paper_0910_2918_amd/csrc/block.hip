@@ -219,6 +219,88 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
   }
 }
 
+// The same stencil step for S sources per workgroup that share each link
+// load: 2 S lanes per site (lane l: side l & 1, source (l >> 1) % S of the
+// workgroup's group blockIdx.y), 32 / S sites per wave.  The lanes of a site
+// ask for the same link entry in the same load instruction, which the
+// memory pipeline serves once, so the links are fetched once per site for
+// all S sources; each lane's arithmetic is that of the one-source kernel.
+// Partial sums per source of the group.  Lanes of a source past the last or
+// of a broken-down source hop like the others (on valid vectors) and write
+// nothing.
+template <int NG, int S>
+__global__ void __launch_bounds__(BT) k_blkS(Geom g, LinksPlain<double> lk, double diag, double eft, double ebt,
+                                              int j, BArgs a) {
+  constexpr int M = 12 / NG;
+  constexpr int NSB = (BT / 64) / NG;
+  constexpr int SPW = 32 / S;  // sites per wave
+  __shared__ XBuf<double, NG> xb;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int gi = w % NG, sb = w / NG;
+  const int f = lane & 1;  // 0: A v_j, 1: A^dag w_j
+  const int sl = (lane >> 1) % S;
+  const int src0 = blockIdx.y * S + sl;
+  const bool have = src0 < a.r;
+  const int src = have ? src0 : a.r - 1;
+  const bool run = have && a.flags[src] == 0;
+  const C64* in = f ? colw(a, src, j) : colv(a, src, j);
+  const int s = (xcd_block() * NSB + sb) * SPW + (lane >> 1) / S;
+  const bool live = s < g.V;
+  C64 mine[M];
+  hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, xb, w, lane, mine);  // dead lanes hop at site 0
+  __syncthreads();
+  const size_t kk = (size_t)src * (a.k + 1);
+  const double svj = a.sv[kk + j];
+  const C64 swj = a.sw[kk + j];
+  C64 scale = f ? swj : mk(svj, 0.0), sub = mk(0.0, 0.0);
+  if (j > 0) {
+    const C64 bm = a.beta[(size_t)src * a.k + j - 1], dm = a.delta[(size_t)src * a.k + j - 1];
+    sub = f ? cmul(dm, a.sw[kk + j - 1]) : a.sv[kk + j - 1] * bm;
+  }
+  const C64* prev = f ? colw(a, src, j > 0 ? j - 1 : 0) : colv(a, src, j > 0 ? j - 1 : 0);
+  C64* out = f ? vq(a, src) : vp(a, src);
+  const C64* wj = colw(a, src, j);
+  double dre = 0.0, dim = 0.0;
+  if (live && run) {
+    int se = s;
+    asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
+#pragma unroll
+    for (int cl = 0; cl < M; ++cl) {
+      const int cc = gi * M + cl;
+      const C64 hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
+      const size_t i = sidx<double>(g.V, cc, se);
+      C64 av = diag * in[i] - 0.5 * hs;
+      if (cc >= 6) av = mk(-av.re, -av.im);
+      C64 o = cmul(scale, av);
+      if (j > 0) o = o - cmul(sub, prev[i]);
+      out[i] = o;
+      if (f == 0) {
+        const C64 t = cmulc(wj[i], av);
+        dre += t.re;
+        dim += t.im;
+      }
+    }
+  }
+  double v[2 * S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    v[2 * t] = sl == t ? dre : 0.0;
+    v[2 * t + 1] = sl == t ? dim : 0.0;
+  }
+  bsum<2 * S>(v);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      const int st = blockIdx.y * S + t;
+      if (st < a.r) {
+        double* p1 = a.part1 + (size_t)st * 2 * a.nb1;
+        p1[blockIdx.x] = v[2 * t];
+        p1[a.nb1 + blockIdx.x] = v[2 * t + 1];
+      }
+    }
+}
+
 // v_hat = p - alpha_j v_j, w_hat = q - conj(alpha_j) w_j into column j + 1,
 // partial sums of s = w_hat^dag v_hat, |v_hat|^2, |w_hat|^2; second sweep:
 // y += lc_{j+1} v_hat
@@ -339,7 +421,26 @@ int nb_elem_b(size_t n) {
 // one sweep of the basis for every source: steps 0 .. kmax - 1; with
 // profile = n > 0 the stencil and update launches of every n-th step carry
 // HIP events (collected by prof_collect)
-int sweep(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int kmax, int profile, hipStream_t st) {
+// one stencil step for every source: ng direction groups, grp sources per
+// workgroup (1: k_blk1; 2, 4: k_blkS); a.nb1 must be blk_nb1(g, ng, grp)
+void launch_blk1(const Geom& g, const LinksPlain<double>& lk, int ng, int grp, double m_w, double eft, double ebt,
+                 int j, const BArgs& a, hipEvent_t e0, hipEvent_t e1, hipStream_t st) {
+  const dim3 gr1(a.nb1, a.r), grS(a.nb1, (a.r + grp - 1) / grp);
+#define NK_BLK(NG_, S_)                                                                                        \
+  if (ng == NG_ && grp == S_) {                                                                                \
+    if (S_ == 1)                                                                                               \
+      hipExtLaunchKernelGGL(k_blk1<NG_>, gr1, dim3(BT), 0, st, e0, e1, 0, g, lk, 4.0 + m_w, eft, ebt, j, a);  \
+    else                                                                                                       \
+      hipExtLaunchKernelGGL((k_blkS<NG_, S_>), grS, dim3(BT), 0, st, e0, e1, 0, g, lk, 4.0 + m_w, eft, ebt, j, \
+                            a);                                                                                \
+    return;                                                                                                    \
+  }
+  NK_BLK(2, 1) NK_BLK(2, 2) NK_BLK(2, 4) NK_BLK(4, 1) NK_BLK(4, 2) NK_BLK(4, 4)
+#undef NK_BLK
+}
+
+int sweep(nk_lattice* lat, const BArgs& a, int ng, int grp, double m_w, double mu, int kmax, int profile,
+          hipStream_t st) {
   const Geom& g = lat->g;
   const LinksPlain<double> lk{lat->U64.as<C64>(), g.V};
   hipLaunchKernelGGL(k_bstart, dim3(a.nb2, a.r), dim3(BT), 0, st, a);
@@ -351,12 +452,7 @@ int sweep(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int km
     if (timed)
       for (auto& e : ev)
         if (int r = prof_event(lat, &e)) return r;
-    if (ng == 2)
-      hipExtLaunchKernelGGL(k_blk1<2>, dim3(a.nb1, a.r), dim3(BT), 0, st, ev[0], ev[1], 0, g, lk, 4.0 + m_w, eft,
-                            ebt, j, a);
-    else
-      hipExtLaunchKernelGGL(k_blk1<4>, dim3(a.nb1, a.r), dim3(BT), 0, st, ev[0], ev[1], 0, g, lk, 4.0 + m_w, eft,
-                            ebt, j, a);
+    launch_blk1(g, lk, ng, grp, m_w, eft, ebt, j, a, ev[0], ev[1], st);
     hipLaunchKernelGGL(k_bred1, dim3(a.r), dim3(BT), 0, st, a, j);
     hipExtLaunchKernelGGL(k_blk2, dim3(a.nb2, a.r), dim3(BT), 0, st, ev[2], ev[3], 0, a, j);
     if (timed) {
@@ -373,7 +469,7 @@ int sweep(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int km
 // private stream) and cached on the handle under its launch arguments; the
 // sweep has kernel launches only, so every replay is the same work as the
 // direct launches, bit for bit
-int sweep_graph(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, int kmax, hipStream_t st) {
+int sweep_graph(nk_lattice* lat, const BArgs& a, int ng, int grp, double m_w, double mu, int kmax, hipStream_t st) {
   // the key: every launch argument, field by field (no padding bytes)
   std::vector<char> kb;
   auto put = [&](const auto& v) {
@@ -382,7 +478,7 @@ int sweep_graph(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, 
   };
   put(a.base), put(a.n), put(a.nslots), put(a.ncols), put(a.store), put(a.r), put(a.k);
   put(a.alpha), put(a.beta), put(a.delta), put(a.sv), put(a.sw), put(a.flags), put(a.part1), put(a.part2);
-  put(a.nb1), put(a.nb2), put(a.lc), put(a.kused), put(ng), put(kmax), put(m_w), put(mu);
+  put(a.nb1), put(a.nb2), put(a.lc), put(a.kused), put(ng), put(grp), put(kmax), put(m_w), put(mu);
   put(lat->U64.p), put(lat->g.V);
   hipGraphExec_t exec = nullptr;
   for (auto& gr : lat->graphs)
@@ -391,7 +487,7 @@ int sweep_graph(nk_lattice* lat, const BArgs& a, int ng, double m_w, double mu, 
     if (!lat->cap_stream) NK_HIP(hipStreamCreateWithFlags(&lat->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     NK_HIP(hipStreamBeginCapture(lat->cap_stream, hipStreamCaptureModeRelaxed));
-    const int e = sweep(lat, a, ng, m_w, mu, kmax, 0, lat->cap_stream);
+    const int e = sweep(lat, a, ng, grp, m_w, mu, kmax, 0, lat->cap_stream);
     const hipError_t ec = hipStreamEndCapture(lat->cap_stream, &graph);
     if (e) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -432,7 +528,13 @@ static int block_range(nk_lattice* lat, const nk_sign_params* p, const int* ell,
   // one-source FP64 two-sided kernel when it has run on this handle
   const int tuned = lat->k1_groups[0][NK_PREC_FP64];
   const int ng = tuned ? tuned : NK_GROUPS;
-  a.nb1 = (g.V + 32 * (4 / ng) - 1) / (32 * (4 / ng));
+  // workgroups of the stencil step with grp sources per workgroup; the
+  // partial sums are sized for the most (grp = 4)
+  auto nb1_of = [&](int grp) {
+    const int spb = (32 / grp) * (4 / ng);
+    return (g.V + spb - 1) / spb;
+  };
+  a.nb1 = nb1_of(4);
   a.nb2 = nb_elem_b(n);
   if (lat->bvec.ensure((size_t)r * a.nslots * colbytes)) return NK_ENOMEM;
   a.base = lat->bvec.as<C64>();
@@ -498,12 +600,50 @@ static int block_range(nk_lattice* lat, const nk_sign_params* p, const int* ell,
   NK_HIP(hipMemsetAsync(a.flags, 0, r * sizeof(int), st));
   NK_HIP(hipMemsetAsync(a.beta, 0, (size_t)r * k * sizeof(C64), st));
   NK_HIP(hipMemsetAsync(a.delta, 0, (size_t)r * k * sizeof(C64), st));
+  // sources per workgroup of the stencil step: chosen once per handle by
+  // timing the step with 1, 2 and 4 (five launches each at step 0, after the
+  // start kernels; the real sweep repeats them); a larger group is taken only
+  // when it is more than 5% faster, so that timing noise does not change the
+  // kernel, and so the grouping of the partial sums, from one process to the
+  // next
+  int& grp = lat->blk_group[ng == 2 ? 0 : 1];
+  if (grp == 0) {
+    const LinksPlain<double> lk{lat->U64.as<C64>(), g.V};
+    hipLaunchKernelGGL(k_bstart, dim3(a.nb2, a.r), dim3(BT), 0, st, a);
+    hipLaunchKernelGGL(k_bred2, dim3(a.r), dim3(BT), 0, st, a, 0);
+    hipEvent_t t0, t1;
+    NK_HIP(hipEventCreate(&t0));
+    NK_HIP(hipEventCreate(&t1));
+    float best = INFINITY;
+    int pick = 1;
+    for (int gsz : {1, 2, 4}) {
+      BArgs at = a;
+      at.nb1 = nb1_of(gsz);
+      launch_blk1(g, lk, ng, gsz, p->m_w, exp(p->mu), exp(-p->mu), 0, at, nullptr, nullptr, st);
+      NK_HIP(hipEventRecord(t0, st));
+      for (int rep = 0; rep < 5; ++rep)
+        launch_blk1(g, lk, ng, gsz, p->m_w, exp(p->mu), exp(-p->mu), 0, at, nullptr, nullptr, st);
+      NK_HIP(hipEventRecord(t1, st));
+      NK_HIP(hipEventSynchronize(t1));
+      float ms = 0.f;
+      NK_HIP(hipEventElapsedTime(&ms, t0, t1));
+      if (ms < 0.95f * best) {
+        best = ms;
+        pick = gsz;
+      }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    NK_HIP(hipGetLastError());
+    grp = pick;
+  }
+  a.nb1 = nb1_of(grp);
   // (graph replays carry no events: profiling times the direct launches)
   lat->evkind.clear();
   lat->evnext = 0;
   auto run_sweep = [&](const BArgs& args, int kmax) {
-    return p->block == 2 ? sweep_graph(lat, args, ng, p->m_w, p->mu, kmax, st)
-                         : sweep(lat, args, ng, p->m_w, p->mu, kmax, p->profile, st);
+    return p->block == 2 ? sweep_graph(lat, args, ng, grp, p->m_w, p->mu, kmax, st)
+                         : sweep(lat, args, ng, grp, p->m_w, p->mu, kmax, p->profile, st);
   };
   if (int e = run_sweep(a, k)) return e;
   NK_HIP(hipEventRecord(ev[1], st));

@@ -215,6 +215,9 @@ struct nk_lattice {
   // autotuned direction groups of the outer-recurrence stencil kernel,
   // [hermitian][precision]; 0 = not tuned yet
   int k1_groups[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  // sources per workgroup of the lockstep stencil kernel (1, 2 or 4), per
+  // direction-group count (index 0: two groups, 1: four); 0 = not tuned yet
+  int blk_group[2] = {0, 0};
   nk::DevBuf tunebuf;  // scratch coefficients of the autotuner
   // optional per-launch timing of the outer-recurrence kernels
   std::vector<hipEvent_t> evpool;

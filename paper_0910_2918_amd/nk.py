@@ -79,6 +79,7 @@ EXPORTS = (
     "nk_overlap_apply_device",
     "nk_overlap_solve_device",
     "nk_stencil_groups",
+    "nk_block_group",
     "nk_rh_tile_force",
     "nk_rh_tile_choice",
     "nk_rh_newton_schulz",
@@ -198,6 +199,7 @@ def library():
         "nk_overlap_solve_device": (C.c_int, [vp, P(nk_sign_params), i32, vp, vp, vp, C.c_double, i32, vp, vp,
                                               P(i32), P(C.c_double), vp]),
         "nk_stencil_groups": (C.c_int, [vp, i32, i32]),
+        "nk_block_group": (C.c_int, [vp, i32]),
         "nk_rh_tile_force": (C.c_int, [i32, i32, i32]),
         "nk_rh_newton_schulz": (C.c_int, [i32]),
         "nk_stream_device": (C.c_int, [i32, C.c_int64, vp, vp, vp, i32, vp]),
@@ -240,6 +242,11 @@ def _hptr(a: np.ndarray):
     if a.dtype != np.complex128 or not a.flags["C_CONTIGUOUS"]:
         raise ValueError("expected a C-contiguous complex128 array")
     return C.c_void_p(a.ctypes.data)
+
+
+def nk_block_group(h, set: int = 0) -> int:
+    """Sources per workgroup of the lockstep stencil kernel: set 1, 2 or 4 to fix it (0: query); returns the previous choice."""
+    return _check(library().nk_block_group(h, int(set)))
 
 
 def nk_stencil_groups(h, precision: int = 0, hermitian: bool = False) -> int:

@@ -198,3 +198,37 @@ def test_full_size_batching_configuration():
         b.nk_sign_apply_device(lat.h, b.nk_sign_params_default(k=k, mu=mu, ell=ells[s]), X[s].contiguous(), y1)
         assert float(torch.linalg.vector_norm(Y[s] - y1) / torch.linalg.vector_norm(y1)) < 1e-12
     lat.close()
+
+
+@pytest.mark.parametrize("grp", [1, 2, 4])
+def test_block_group_sizes(grp):
+    """Every lockstep group size (1, 2 or 4 sources per workgroup sharing
+    each link load), on 8^4 with 5 sources (a ragged last group for 2 and 4),
+    against the one-at-a-time path within method_bound of that path's own
+    rounding sensitivity, two-pass against one-pass, and graph replays
+    bit-identical to direct launches."""
+    b = nk()
+    dims, mu, k = (8, 8, 8, 8), 0.3, 200
+    lat, u = make_lattice(dims, 0.6, seed=3)
+    xs = latgen.random_sources(dims, 5, 13)
+    ells = [30, 50, 20, 60, 40]
+    b.nk_block_group(lat.h, grp)
+    banner(f"block group {grp}: 8^4 r=5 k={k}")
+    yb, _, rc = _run(lat, xs, k=k, ell_per_rhs=ells, block=1)
+    assert rc == 0 and b.nk_block_group(lat.h) == grp
+    ys, _, _ = _run(lat, xs, k=k, ell_per_rhs=ells, block=0)
+    yp, _, _ = _run(lat, np.stack([perturbed(xs[s], seed=200 + s) for s in range(5)]), k=k, ell_per_rhs=ells,
+                    block=0)
+    for s in range(5):
+        sens = rel(yp[s], ys[s])
+        print(f"[gap] group {grp} s={s}: block vs single {rel(yb[s], ys[s]):.3e}, sensitivity {sens:.3e}",
+              flush=True)
+        assert rel(yb[s], ys[s]) <= method_bound(sens)
+    y2, i2, _ = _run(lat, xs, k=k, ell_per_rhs=ells, block=1, two_pass=1)
+    assert i2.two_pass == 1
+    for s in range(5):
+        assert rel(y2[s], yb[s]) < 1e-13
+    yg1, _, _ = _run(lat, xs, k=k, ell_per_rhs=ells, block=2)
+    yg2, _, _ = _run(lat, xs, k=k, ell_per_rhs=ells, block=2)
+    assert np.array_equal(yg1, yb) and np.array_equal(yg2, yb)
+    lat.close()
