@@ -10,8 +10,11 @@
 //     Ritz value of H^2 in the current block;
 //   * the block is orthonormalised by Cholesky QR, twice;
 //   * Rayleigh-Ritz with H^2 (no spurious interior Ritz values, unlike with
-//     the indefinite H) rotates it to Ritz vectors, whose eigenvalue of H is
-//     their Rayleigh quotient;
+//     the indefinite H over the whole block) rotates it to Ritz vectors;
+//     then Rayleigh-Ritz with H on the leading q >= m of them (q grows past
+//     m while their H^2 values repeat) splits the pairs lambda, -lambda that
+//     H^2 cannot tell apart (the free field's spectrum is exactly symmetric);
+//     the eigenvalue of H of each vector is its Rayleigh quotient;
 //   * it stops when the m leading residuals |H r - lambda r| are below
 //     tol * sqrt(b2).
 // Vector work (stencil, Chebyshev steps, Gram matrices, block combinations)
@@ -432,6 +435,36 @@ int eig_hermitian(nk_lattice* lat, double m_w, int m, int p, int degree, double 
     std::vector<cd> g, q;
     if (int e = gram(w, Wb, g)) return e;  // V^dag H^2 V = (H V)^dag (H V), exactly Hermitian by construction
     dense::jacobi_herm(g, p, t2, q);
+    if (int e = combine(w, V, q, p, T)) return e;
+    std::swap(V, T);
+    if (int e = combine(w, Wb, q, p, T)) return e;
+    std::swap(Wb, T);
+    // then with H itself on the leading nq >= m vectors (nq grows past m
+    // while the H^2 values repeat), which splits pairs lambda, -lambda that
+    // H^2 cannot tell apart; sorted by |theta|
+    int nq = m;
+    while (nq < p && std::fabs(t2[nq] - t2[nq - 1]) <= 1e-8 * std::fabs(t2[nq])) ++nq;
+    std::vector<cd> kq, qq;
+    if (int e = gram2(w, V, Wb, nq, kq)) return e;
+    for (int j = 0; j < nq; ++j)
+      for (int i = 0; i <= j; ++i) {
+        const cd h = 0.5 * (kq[i + (size_t)j * nq] + std::conj(kq[j + (size_t)i * nq]));
+        kq[i + (size_t)j * nq] = i == j ? cd(h.real(), 0.0) : h;
+        kq[j + (size_t)i * nq] = i == j ? cd(h.real(), 0.0) : std::conj(h);
+      }
+    std::vector<double> tq;
+    dense::jacobi_herm(kq, nq, tq, qq);
+    std::vector<int> idx(nq);
+    for (int i = 0; i < nq; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return std::fabs(tq[x]) < std::fabs(tq[y]); });
+    q.assign((size_t)p * p, cd(0.0, 0.0));
+    for (int j = 0; j < p; ++j) {
+      if (j < nq) {
+        for (int i = 0; i < nq; ++i) q[i + (size_t)j * p] = qq[i + (size_t)idx[j] * nq];
+      } else {
+        q[j + (size_t)j * p] = 1.0;
+      }
+    }
     if (int e = combine(w, V, q, p, T)) return e;
     std::swap(V, T);
     if (int e = combine(w, Wb, q, p, T)) return e;

@@ -3,6 +3,8 @@
 * 2x2x4x4: the 16 eigenvalues of gamma5 Dw(0) smallest in modulus against the
   oracle's dense eigen-decomposition (1e-10), orthonormal eigenvectors, and
   residuals |H r - lambda r| recomputed with the oracle's stencil;
+* 2x2x4x4 free field: an exactly symmetric cluster lambda = +1, -1 (24 each)
+  against the closed-form momentum-space spectrum;
 * what they are for: deflating a nested sign application on 2x4x4x4 with the
   GPU's own eigenpairs is as accurate as with the dense ones, and more
   accurate than no deflation at the same k;
@@ -14,6 +16,7 @@ import pytest
 import latgen
 from oracle import deflation as DF
 from oracle import dense as D
+from oracle import freefield as FF
 from oracle import wilson as W
 from tests.gpu_helpers import M_W, banner, make_lattice, nk, rel, to_dev, to_host, torch_cuda
 
@@ -41,6 +44,36 @@ def test_matches_dense():
     shape = (4, 4, 2, 2, 4, 3)
     for i in range(16):
         hr = W.a_apply(u, r[:, i].reshape(shape), M_W, 0.0).reshape(-1)
+        assert np.linalg.norm(hr - lam[i] * r[:, i]) < 2e-10
+    lat.close()
+
+
+@pytest.mark.parametrize("m", [48, 40])
+def test_free_field_symmetric_pairs(m):
+    """U = 1 on 2x2x4x4 at m_w = -1: the smallest |lambda| of gamma5 Dw(0) is
+    1, with 24 eigenvectors at +1 and 24 at -1 (the plane waves of the lowest
+    temporal momenta and their doublers), an exactly symmetric cluster that
+    H^2 cannot split.  Against the closed-form momentum-space spectrum: at
+    m = 48 the sorted eigenvalues, at m = 40 (inside the cluster) |lambda| = 1;
+    both with residuals from the oracle's free-field operator and orthonormal
+    vectors."""
+    dims = (2, 2, 4, 4)
+    banner(f"eigensolver free field 2x2x4x4 mu=0 m={m} p=64")
+    lat, u = make_lattice(dims, 0.0, unit=True)
+    lam, r, passes, resid, rc = _eig(lat, dims, m, 64, degree=20, tol=1e-11, maxit=60)
+    print(f"passes {passes} resid {resid:.2e}", flush=True)
+    assert rc == 0 and resid <= 1e-11 * 11.0
+    ev = np.repeat(np.linalg.eigvals(FF.g5dw_momentum(dims, M_W, 0.0).reshape(-1, 4, 4)).ravel().real, 3)
+    exact = np.sort(ev[np.argsort(np.abs(ev), kind="stable")[:48]])
+    assert np.max(np.abs(exact)) - 1.0 < 1e-12 and np.sum(exact > 0) == 24
+    if m == 48:
+        assert np.max(np.abs(np.sort(lam) - exact)) < 1e-10
+    else:
+        assert np.max(np.abs(np.abs(lam) - 1.0)) < 1e-10
+    assert np.linalg.norm(r.conj().T @ r - np.eye(m)) < 1e-12
+    shape = (4, 4, 2, 2, 4, 3)
+    for i in range(m):
+        hr = FF.g5dw_apply_free(r[:, i].reshape(shape), M_W, 0.0).reshape(-1)
         assert np.linalg.norm(hr - lam[i] * r[:, i]) < 2e-10
     lat.close()
 
