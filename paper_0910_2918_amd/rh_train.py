@@ -33,14 +33,17 @@ from paper_0910_2918_amd import nk  # noqa: E402
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "rh_scaling_weights.npy")
 
 # (dims, mu, link width, outer k, largest inner ell, gauge fields, sources per
-# field): the workloads of the 4^4, 8^4 and 16^4 runs
+# field): the workloads of the 4^4, 8^4 and 16^4 runs; with every ell from 16
+# up (ELL_STEP = 1) about 18,700 matrices, the last gauge field of each
+# configuration held out
 CONFIGS = [
-    ((4, 4, 4, 4), 0.0, 0.4, 150, 120, 8, 2),
-    ((8, 8, 8, 8), 0.3, 0.6, 400, 200, 6, 2),
-    ((8, 8, 8, 8), 0.0, 0.6, 400, 200, 4, 2),
-    ((16, 16, 16, 16), 0.3, 0.8, 600, 300, 3, 1),
-    ((16, 16, 16, 16), 0.0, 0.8, 600, 300, 3, 1),
+    ((4, 4, 4, 4), 0.0, 0.4, 150, 120, 20, 2),
+    ((8, 8, 8, 8), 0.3, 0.6, 400, 200, 12, 3),
+    ((8, 8, 8, 8), 0.0, 0.6, 400, 200, 8, 3),
+    ((16, 16, 16, 16), 0.3, 0.8, 600, 300, 6, 1),
+    ((16, 16, 16, 16), 0.0, 0.8, 600, 300, 6, 1),
 ]
+ELL_STEP = 1
 
 
 def tridiag_dense(a, b, d) -> np.ndarray:
@@ -94,7 +97,7 @@ class Data:
         self.n = len(mats)
 
 
-def prepare(mats) -> Data:
+def prepare(mats, log=None) -> Data:
     import torch
 
     B = len(mats)
@@ -109,7 +112,11 @@ def prepare(mats) -> Data:
         fc = torch.zeros((len(part), nk.NK_MLP_IN), dtype=torch.float32, device="cuda")
         nk.nk_rh_features_device(torch.from_numpy(S).cuda(), [m.shape[0] for m in part], fc)
         feat[c0:c0 + len(part)] = fc
-    lams = [np.linalg.eigvals(m) for m in mats]
+    lams = []
+    for i, m in enumerate(mats):
+        lams.append(np.linalg.eigvals(m))
+        if log and (i + 1) % 4000 == 0:
+            log(f"[rh_train] eigenvalues of {i + 1} / {B} matrices")
     off = np.zeros(B + 1, np.int32)
     off[1:] = np.cumsum([len(x) for x in lams])
     lam = torch.from_numpy(np.concatenate(lams).astype(np.complex128)).cuda()
@@ -212,7 +219,7 @@ def main(argv=None) -> int:
     import latgen
 
     t0 = time.time()
-    groups = collect(seed0=args.seed)
+    groups = collect(ell_step=ELL_STEP, seed0=args.seed)
     # hold out the last gauge field of every configuration
     tr, hold = [], []
     gi = 0
@@ -222,7 +229,7 @@ def main(argv=None) -> int:
             gi += 1
     print(f"[rh_train] {len(tr)} training and {len(hold)} held-out matrices "
           f"({time.time() - t0:.1f} s)", flush=True)
-    data = prepare(tr)
+    data = prepare(tr, log=lambda m: print(m, flush=True))
     p0 = standardise(latgen.mlp_init(args.seed), data)
     import torch
 

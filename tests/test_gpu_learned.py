@@ -219,6 +219,35 @@ def test_training_on_gpu_lowers_the_loss_and_keeps_the_limit():
         assert np.linalg.norm(a - r) <= 1e-9 * np.linalg.norm(r)
 
 
+def test_shipped_model_no_worse_than_determinant_scaling():
+    """The committed model against determinant scaling on H_ell from gauge
+    fields and sources that training never saw (8^4 mu = 0.3 and mu = 0, 4^4
+    mu = 0; seeds 70000 and up): the mean Roberts-Higham iteration count with
+    NK_RH_LEARNED is not above that with NK_RH_DET (both deterministic), and
+    the sign function is the same."""
+    import os
+
+    b = nk()
+    from paper_0910_2918_amd import rh_train
+
+    if not os.path.exists(rh_train.WEIGHTS):
+        pytest.skip("no trained model shipped")
+    model = np.load(rh_train.WEIGHTS).astype(np.float32)
+    hold = _method_mats((8, 8, 8, 8), 0.3, 0.6, 400, 200, 70000, 1, 1, ell_min=16, ell_step=3) + \
+        _method_mats((8, 8, 8, 8), 0.0, 0.6, 400, 200, 71000, 1, 1, ell_min=16, ell_step=3) + \
+        _method_mats((4, 4, 4, 4), 0.0, 0.4, 150, 120, 72000, 1, 2, ell_min=16, ell_step=3)
+    banner(f"shipped model vs determinant scaling on {len(hold)} unseen H_ell")
+    s_det, it_det = rh_train.rh_iterations(hold, b.NK_RH_DET)
+    s_lrn, it_lrn = rh_train.rh_iterations(hold, b.NK_RH_LEARNED, model)
+    _, it_none = rh_train.rh_iterations(hold, b.NK_RH_NONE)
+    print(f"mean RH iterations: none {it_none.mean():.3f}, det {it_det.mean():.3f}, learned {it_lrn.mean():.3f}; "
+          f"learned fewer on {int(np.sum(it_lrn < it_det))}, more on {int(np.sum(it_lrn > it_det))} of {len(hold)}",
+          flush=True)
+    assert it_lrn.mean() <= it_det.mean()
+    for a, r in zip(s_lrn, s_det):
+        assert np.linalg.norm(a - r) <= 1e-9 * np.linalg.norm(r)
+
+
 def test_learned_scaling_end_to_end_same_result():
     """NK_RH_LEARNED with an installed model: the same vector as the unscaled
     method (sgn(mu S) = sgn(S)), within rounding."""
