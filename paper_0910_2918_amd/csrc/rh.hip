@@ -59,14 +59,6 @@ __device__ __forceinline__ C64 crecip1(C64 a) {
   return mk(ldexp(ar * q, -e), ldexp(-ai * q, -e));
 }
 
-__device__ __forceinline__ C64 cinv(C64 a) {
-  // 1 / a, scaled to avoid overflow in |a|^2
-  const double s = fmax(fabs(a.re), fabs(a.im));
-  const double ar = a.re / s, ai = a.im / s;
-  const double d = (ar * ar + ai * ai) * s;
-  return mk(ar / d, -ai / d);
-}
-
 typedef double nk_d4 __attribute__((ext_vector_type(4)));
 
 // the 32-bit pivot key of a panel row r < 4096 (never zero)
@@ -561,7 +553,7 @@ __device__ __forceinline__ unsigned piv_key32(double v, int r) {
   return (__float_as_uint((float)v) & ~255u) | (unsigned)(255 - r);
 }
 
-template <int SQ>  // rows per thread; n <= 4 SQ
+template <int SQ>  // rows per thread, at least ceil(n / floor(512 / n)) (the host picks it)
 __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restrict__ nvec, C64* __restrict__ S_b,
                                                    int scaling, const double* __restrict__ mu_sched, int mu_steps,
                                                    int maxit, double tol, int* __restrict__ iters,
@@ -626,13 +618,13 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
           const unsigned kk = piv_key32(fabs(v.re) + fabs(v.im), r);
           key = kk > key ? kk : key;
         }
-      key = __reduce_max_sync(~0ull, key);
+      key = wave_max_u32(key);
       // every unused row has a nonzero key, and one is unused while t < n; the
       // fallback only keeps the index in range should that ever not hold
       const int pr = key ? 255 - (int)(key & 255u) : t;
       const C64 pv = s_col[par][pr];
       if (!(fabs(pv.re) + fabs(pv.im) > 0.0)) bad = 1;
-      const C64 d = cinv(pv);
+      const C64 d = crecip1(pv);
       if (scaling != NK_RH_NONE) {
         int ex;
         dm = frexp(dm * norm2(pv), &ex);
@@ -944,7 +936,19 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     int rps = 0;  // largest rows-per-thread over the batch
     for (int b = 0; b < batch; ++b)
       if (n_host[b] > 0) rps = std::max(rps, (n_host[b] + ST_RH / n_host[b] - 1) / (ST_RH / n_host[b]));
-    if (rps <= 16)
+    // the smallest rows-per-thread bound that covers the batch: rows past a
+    // thread's own are computed and discarded, so a tight bound halves the
+    // per-pivot work each time it halves
+    if (rps <= 2)
+      hipLaunchKernelGGL(k_rh_small<2>, dim3(batch), dim3(ST_RH), 0, st, ld, nvec, S, scaling, mdev, mu_steps, maxit,
+                         tol, act, sing);
+    else if (rps <= 4)
+      hipLaunchKernelGGL(k_rh_small<4>, dim3(batch), dim3(ST_RH), 0, st, ld, nvec, S, scaling, mdev, mu_steps, maxit,
+                         tol, act, sing);
+    else if (rps <= 8)
+      hipLaunchKernelGGL(k_rh_small<8>, dim3(batch), dim3(ST_RH), 0, st, ld, nvec, S, scaling, mdev, mu_steps, maxit,
+                         tol, act, sing);
+    else if (rps <= 16)
       hipLaunchKernelGGL(k_rh_small<16>, dim3(batch), dim3(ST_RH), 0, st, ld, nvec, S, scaling, mdev, mu_steps, maxit,
                          tol, act, sing);
     else
