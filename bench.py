@@ -292,7 +292,8 @@ def main() -> int:
     ap.add_argument("--probe", action="store_true",
                     help="short run for hardware counters: a copy kernel of known size (1 GiB read, 1 GiB "
                          "written, larger than the 256 MB Infinity Cache) three times, then one application "
-                         "at k=20, l=5 of the same workload (same stencil dispatches as the timed run)")
+                         "at k=20, l=5 of the same workload (same stencil dispatches as the timed run), one "
+                         "deflated application and four sources in lockstep at the same k, l")
     ap.add_argument("--calibrate", action="store_true",
                     help="print the relative error of plain and nested runs over a grid of (k, l)")
     args = ap.parse_args()
@@ -352,6 +353,11 @@ def main() -> int:
         rd, ld = (torch.from_numpy(a / np.linalg.norm(a, axis=1, keepdims=True)).to(dev).reshape(-1) for a in dv)
         lamd = np.array([1.0 if i % 2 == 0 else -1.0 for i in range(md)], dtype=np.complex128)
         nk.nk_sign_apply_deflated_device(lat.h, params(20, 5), lamd, rd, ld, x, y)
+        # four sources in lockstep (block = 1) at k = 20, l = 5: the lockstep
+        # stencil's counters (k_blk1, one source per workgroup as tuned)
+        xb4 = torch.from_numpy(latgen.random_sources(DIMS, 4, 1).reshape(-1)).to(dev)
+        yb4 = torch.empty_like(xb4)
+        nk.nk_sign_apply_device(lat.h, params(20, 5, nrhs=4, block=1), xb4, yb4)
         torch.cuda.synchronize()
         gbs = 2 * n * 16 / (min(times) / 1e3) / 1e9
         print(json.dumps({"probe": "done", "copy_bytes_read": n * 16, "copy_bytes_written": n * 16,
@@ -420,6 +426,7 @@ def main() -> int:
     nside = max(1, args.steps // 2)
     t_plain, info_p = timed(nside, k=args.k, ell=0)
     t_nested_u, info_u = timed(nside, k=args.k, ell=args.ell)
+    t_nested_d, info_d = timed(nside, k=args.k, ell=args.ell, scaling=nk.NK_RH_DET)
     # many sources in lockstep (nested, learned scaling): per-source rate
     nb = args.batch
     xb = torch.from_numpy(latgen.random_sources(DIMS, nb, 1).reshape(-1)).to(dev)
@@ -747,7 +754,10 @@ def main() -> int:
             "reference": f"non-nested k={kref}",
         },
         "forms": {
-            "nested_learned": {"applies_per_s": 1.0 / t_nested, "rh_iters": rh_iters},
+            "nested_learned": {"applies_per_s": 1.0 / t_nested, "rh_iters": rh_iters,
+                               "small_ms": ph["small"] / args.steps},
+            "nested_determinant": {"applies_per_s": 1.0 / t_nested_d, "rh_iters": info_d["rh_iters"],
+                                   "small_ms": info_d["t_small_ms"] / nside},
             "nested_unscaled": {"applies_per_s": 1.0 / t_nested_u, "rh_iters": info_u["rh_iters"],
                                 "small_ms": info_u["t_small_ms"] / nside},
             "plain_unscaled": {"applies_per_s": 1.0 / t_plain, "rh_iters": info_p["rh_iters"],
@@ -785,7 +795,7 @@ def main() -> int:
         "learned_scaling_24x24x24x24": rh24,
         "rh_dense": rh_dense,
         "two_pass": two_pass,
-        "deflation_m32": deflation,
+        "deflation": deflation,
         "overlap_solve": overlap_solve,
         "eigensolver_mu0": eig_mu0,
     }
