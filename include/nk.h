@@ -136,7 +136,7 @@ typedef struct nk_sign_info {
   int32_t two_pass;       /* 1 if the lift rebuilt the basis */
   int32_t pad;
   double est;             /* convergence estimate (NaN if not computed) */
-  double rh_residual;     /* |S (S e_1) - e_1| of the final Roberts-Higham iterate S (0 if sgn^2 = 1 holds on e_1) */
+  double rh_residual;     /* |S^2 - I|_F / sqrt(n) of the final Roberts-Higham iterate S of order n (0 when S^2 = I) */
   double t_basis_ms, t_small_ms, t_lift_ms;
   /* with params.profile: summed durations and launch counts of the two
    * outer-recurrence kernels (K1: stencil step, K2: update step); with

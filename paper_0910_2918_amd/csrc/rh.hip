@@ -367,45 +367,6 @@ __global__ void __launch_bounds__(256) k_gjcombine(int ld, int nb, const int* __
 }
 
 
-// r_b = |S (S e_1) - e_1| per matrix, in two steps: one wave per row i forms
-// |(S (S e_1))_i - delta_i0|^2 (lanes over the row, a fixed-order wave sum),
-// then one workgroup per matrix sums the rows in row order
-__global__ void __launch_bounds__(256) k_rh_resid_rows(int ld, const int* __restrict__ nvec,
-                                                       const C64* __restrict__ S_b, double* __restrict__ rows) {
-  const int b = blockIdx.y;
-  const int n = nvec[b];
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (i >= n) return;
-  const C64* S = S_b + (size_t)b * ld * ld;
-  double re = 0.0, im = 0.0;
-  for (int j = lane; j < n; j += 64) {
-    const C64 t = cmul(S[(size_t)i * ld + j], S[(size_t)j * ld]);
-    re += t.re;
-    im += t.im;
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    re += __shfl_xor(re, o, 64);
-    im += __shfl_xor(im, o, 64);
-  }
-  if (lane == 0) {
-    if (i == 0) re -= 1.0;
-    rows[(size_t)b * ld + i] = re * re + im * im;
-  }
-}
-
-__global__ void __launch_bounds__(256) k_rh_resid_sum(int ld, const int* __restrict__ nvec,
-                                                      const double* __restrict__ rows, double* __restrict__ out) {
-  const int b = blockIdx.x;
-  const int n = nvec[b];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += rows[(size_t)b * ld + i];
-  __shared__ double sh[4];
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) out[b] = sqrt((sh[0] + sh[1]) + (sh[2] + sh[3]));
-}
-
 // ---------------------------------------------------------------------------
 // Newton-Schulz tail of the iteration (an option of this library, not the
 // paper's): once |I - S_n^2|_F < 1/2, X <- X (3 I - X^2) / 2 converges
@@ -518,6 +479,22 @@ __global__ void k_ns_copy(int ld, const int* __restrict__ nvec, const int* __res
     const size_t i = off + (e / n) * ld + (e % n);
     S_b[i] = G_b[i];
   }
+}
+
+// r_b = |S_b^2 - I|_F / sqrt(n_b) from the per-tile partial sums of
+// |I - S^2|_F^2 that k_ns_gemm<0> leaves (tiles x tiles pairs per matrix),
+// summed in tile order by one workgroup per matrix
+__global__ void __launch_bounds__(256) k_rh_resid_sum(int tiles2, const int* __restrict__ nvec,
+                                                      const double* __restrict__ part, double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int n = nvec[b];
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < tiles2; t += 256) acc += part[((size_t)b * tiles2 + t) * 2];
+  __shared__ double sh[4];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[b] = n > 0 ? sqrt(((sh[0] + sh[1]) + (sh[2] + sh[3])) / n) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -893,6 +870,27 @@ int rh_tile_choice(int maxn, int batch, int* nb, int* rm, int* pth, int* tile) {
   return 1;
 }
 
+// |S^2 - I|_F / sqrt(n) of every matrix of the batch into resid_host: one
+// product S S on the matrix cores (k_ns_gemm<0>, which leaves 3 I - S^2 in the
+// scratch buffer G0 and the partial sums of |I - S^2|_F^2), then the sums
+static int rh_residuals(int batch, int ld, int maxn, const int* nvec, const C64* S, double* resid,
+                        double* resid_host, hipStream_t st) {
+  const int ntile = (maxn + 31) / 32;
+  const size_t nsp = (size_t)batch * ntile * ntile * 2;
+  if (g_nsp.ensure(nsp * sizeof(double) + (size_t)batch * sizeof(int))) return NK_ENOMEM;
+  double* part = g_nsp.as<double>();
+  int* all = reinterpret_cast<int*>(part + nsp);
+  std::vector<int> ones(batch, 1);
+  NK_HIP(hipMemcpyAsync(all, ones.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_ns_gemm<0>, dim3(ntile, ntile, batch), dim3(256), 0, st, ld, nvec, all, S, S, g_G0.as<C64>(),
+                     part);
+  hipLaunchKernelGGL(k_rh_resid_sum, dim3(batch), dim3(256), 0, st, ntile * ntile, nvec, part, resid);
+  NK_HIP(hipGetLastError());
+  NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));  // ones stays alive until its copy has been consumed
+  return NK_OK;
+}
+
 int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, int maxit, double tol,
                     int* iters_host, double* resid_host, hipStream_t st) {
   std::lock_guard<std::mutex> lock(g_rh_mu);
@@ -904,7 +902,7 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   const size_t mb = (size_t)batch * ld * ld * sizeof(C64);
   const int nbl = 64;
   if (g_G0.ensure(mb) || g_G1.ensure(mb) || g_int.ensure((size_t)batch * (2 * ld + 4) * sizeof(int)) ||
-      g_dbl.ensure((size_t)batch * (2 * nbl + 4 + ld) * sizeof(double)) || g_mu.ensure((size_t)batch * sizeof(double)))
+      g_dbl.ensure((size_t)batch * (2 * nbl + 4) * sizeof(double)) || g_mu.ensure((size_t)batch * sizeof(double)))
     return NK_ENOMEM;
   int* nvec = g_int.as<int>();
   int* act = nvec + batch;
@@ -914,7 +912,6 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   double* logdet = g_dbl.as<double>();
   double* resid = logdet + batch;
   double* part = resid + batch;
-  double* rrows = part + (size_t)batch * 2 * nbl;  // per-row terms of the residual
   double* mu_dev = g_mu.as<double>();
 
   int maxn = 0;
@@ -958,11 +955,8 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     std::vector<int> sing_h(batch);
     NK_HIP(hipMemcpyAsync(iters_host, act, batch * sizeof(int), hipMemcpyDeviceToHost, st));
     NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
-    if (resid_host) {
-      hipLaunchKernelGGL(k_rh_resid_rows, dim3((maxn + 3) / 4, batch), dim3(256), 0, st, ld, nvec, S, rrows);
-      hipLaunchKernelGGL(k_rh_resid_sum, dim3(batch), dim3(256), 0, st, ld, nvec, rrows, resid);
-      NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
-    }
+    if (resid_host)
+      if (int e = rh_residuals(batch, ld, maxn, nvec, S, resid, resid_host, st)) return e;
     NK_HIP(hipStreamSynchronize(st));
     return rh_outcome(batch, sing_h.data(), maxit);
   }
@@ -1080,11 +1074,8 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   }
   std::vector<int> sing_h(batch);
   NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
-  if (resid_host) {
-    hipLaunchKernelGGL(k_rh_resid_rows, dim3((maxn + 3) / 4, batch), dim3(256), 0, st, ld, nvec, S, rrows);
-    hipLaunchKernelGGL(k_rh_resid_sum, dim3(batch), dim3(256), 0, st, ld, nvec, rrows, resid);
-    NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
-  }
+  if (resid_host)
+    if (int e = rh_residuals(batch, ld, maxn, nvec, S, resid, resid_host, st)) return e;
   NK_HIP(hipStreamSynchronize(st));
   for (int b = 0; b < batch; ++b)
     if (act_h[b] && !sing_h[b]) sing_h[b] = 2;  // still active after maxit iterations

@@ -123,6 +123,31 @@ def test_small_sign_matches_oracle(ritz, ell):
     assert info.rh_residual < 1e-9
 
 
+@pytest.mark.parametrize("k", [100, 150])
+@pytest.mark.parametrize("maxit", [2, 3, 100])
+def test_rh_residual_is_s_squared_minus_one(ritz, k, maxit):
+    """info.rh_residual is |S^2 - I|_F / sqrt(n) of the final Roberts-Higham
+    iterate: against the oracle's iterate after the same number of steps on
+    the plain form's H_k (k = 100 runs the one-workgroup kernel, 150 the
+    blocked inverse), unconverged (2, 3 steps: residual of order one) and
+    converged (below 1e-9)."""
+    mu, H = ritz
+    herm = mu == 0.0
+    b = nk()
+    p = b.nk_sign_params_default(rh_maxit=maxit)
+    z, info, rc = b.nk_small_sign(k, 0, herm, H.alpha[:k], H.beta[:k], H.delta[:k], p)
+    hk = H.dense()[:k, :k]
+    S, it, _ = R.roberts_higham(hk, maxit=maxit)
+    ref = np.linalg.norm(S @ S - np.eye(k)) / np.sqrt(k)
+    print(f"k={k} maxit={maxit}: GPU {info.rh_residual:.6e} oracle {ref:.6e} ({info.rh_iters} / {it} steps)", flush=True)
+    assert info.rh_iters == it
+    if maxit < 100:
+        assert rc == b.NK_WARN_NOTCONV
+        assert abs(info.rh_residual - ref) <= 1e-8 * ref
+    else:
+        assert info.rh_residual < 1e-9 and ref < 1e-9
+
+
 @pytest.mark.parametrize("ell", [1, 20, 45, 150])
 def test_small_sign_arnoldi_matches_oracle(ritz, ell):
     """The Arnoldi inner option against the oracle's Arnoldi (Hessenberg H_l),
