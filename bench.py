@@ -108,7 +108,7 @@ def stream_ceiling(torch, nk, dev, nbytes=1024 ** 3):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("krylov.hip", "stencil.h", "nk_internal.h"):
+    for f in ("krylov.hip", "stencil.h", "nk_internal.h", "layout.hip"):
         with open(os.path.join(ROOT, "paper_0910_2918_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -68,8 +68,20 @@ void geom_init(Geom& g, const int dims[4]) {
     g.stride[d] = st;
     st *= dims[d];
     g.V *= dims[d];
-    g.b[d] = (dims[d] % 4 == 0) ? 4 : 2;
-    g.lb[d] = g.b[d] == 4 ? 2 : 1;
+    // tiles of 16 x 4 x 4 x 4 sites where the extents allow (x first: 16,
+    // else 8, 4 or 2; the others 4, else 2): a tile row holds a whole 16-site
+    // x line, 256 contiguous bytes per spinor component, so x hops stay in
+    // the tile and every cache line a wave touches is used in full
+    const int want = d == 0 ? 16 : 4;
+    int bd = 2;
+    for (int t = want; t >= 4; t >>= 1)
+      if (dims[d] % t == 0) {
+        bd = t;
+        break;
+      }
+    g.b[d] = bd;
+    g.lb[d] = 0;
+    while ((1 << g.lb[d]) < g.b[d]) ++g.lb[d];
     g.nt[d] = dims[d] / g.b[d];
   }
   int ls = 1, lts = 0;

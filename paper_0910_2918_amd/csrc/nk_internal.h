@@ -78,7 +78,8 @@ __host__ __device__ __forceinline__ Cx<R> narrow(Cx<double> a) { return mk<R>((R
 // lattice geometry: dims {Lx, Ly, Lz, Lt}.
 // Canonical (API) site order: ((t Lz + z) Ly + y) Lx + x.
 // Device site order is tiled: the lattice is cut into tiles of b0 x b1 x b2 x b3
-// sites (b = 4 where the extent allows, else 2) and
+// sites (16 x 4 x 4 x 4 where the extents allow; b0 else 8, 4 or 2, the
+// others else 2) and
 //   site = tile * TS + local,  local = ((tl b2 + zl) b1 + yl) b0 + xl,
 //   tile = ((TT n2 + TZ) n1 + TY) n0 + TX,
 // so that one workgroup's sites form a compact hypercube whose neighbours
