@@ -110,10 +110,26 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
   C64 a[RM][NB];
   bool used[RM];
   if constexpr (SG::on) {
-    // sixteen consecutive threads read one row's NB entries (contiguous)
-    for (int e = tid; e < SG::rows * NB; e += PTH) {
-      const int r = e / NB, t = e % NB;
-      s_panel[r][t] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
+    // sixteen consecutive threads read one row's NB entries (contiguous);
+    // sixteen loads per thread go out together before any LDS write, so the
+    // panel costs one memory round trip per batch, not one per entry
+    constexpr int PER = SG::rows * NB / PTH, BMAX = PTH >= 1024 ? 8 : 16, BAT = PER < BMAX ? PER : BMAX;
+    static_assert(PER % BAT == 0, "panel entries per thread in whole batches");
+#pragma unroll
+    for (int q0 = 0; q0 < PER; q0 += BAT) {
+      C64 v[BAT];
+#pragma unroll
+      for (int q = 0; q < BAT; ++q) {
+        const int e = tid + (q0 + q) * PTH, r = e / NB, t = e % NB;
+        v[q] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < BAT; ++q) asm volatile("" : "+v"(v[q].re), "+v"(v[q].im));
+#pragma unroll
+      for (int q = 0; q < BAT; ++q) {
+        const int e = tid + (q0 + q) * PTH;
+        s_panel[e / NB][e % NB] = v[q];
+      }
     }
     __syncthreads();
   }
@@ -164,7 +180,24 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
           for (int u = 0; u < NB; ++u) s_prow[par][u] = a[m][u];
       if (tid == 0) s_piv[t] = pr;
       __syncthreads();
-      const C64 piv = best ? s_prow[par][t] : mk(0.0, 0.0);
+      // the pivot row in registers, all of it read before any use (one LDS
+      // round trip, not one per entry) where the register budget allows it
+      // (up to 512 threads: two waves per SIMD)
+      constexpr bool REGROW = PTH < 1024;
+      C64 prow[REGROW ? NB : 1];
+      if constexpr (REGROW) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) prow[u] = s_prow[par][u];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) asm volatile("" : "+v"(prow[u].re), "+v"(prow[u].im));
+      }
+      auto prow_at = [&](int u) -> C64 {
+        if constexpr (REGROW)
+          return prow[u];
+        else
+          return s_prow[par][u];
+      };
+      const C64 piv = best ? prow_at(t) : mk(0.0, 0.0);
       const bool nz = cabs1(piv) > 0.0;
       if (!nz) bad = 1;
       const C64 d = nz ? crecip1(piv) : mk(0.0, 0.0);
@@ -187,7 +220,7 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
         const double keep = isp ? 0.0 : 1.0;
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-          const C64 p = (u == t) ? mk(1.0, 0.0) : s_prow[par][u];
+          const C64 p = (u == t) ? mk(1.0, 0.0) : prow_at(u);
           const double kr = (u == t) ? 0.0 : keep * a[m][u].re, ki = (u == t) ? 0.0 : keep * a[m][u].im;
           a[m][u] = mk(fma(g.im, p.im, fma(-g.re, p.re, kr)), fma(-g.im, p.re, fma(-g.re, p.im, ki)));
         }
@@ -202,9 +235,21 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
 #pragma unroll
       for (int t = 0; t < NB; ++t) s_panel[tid + m * PTH][t] = a[m][t];
     __syncthreads();
-    for (int e = tid; e < SG::rows * NB; e += PTH) {
-      const int r = e / NB, t = e % NB;
-      if (r < n && t < nbe) Anew[(size_t)r * ld + c0 + t] = s_panel[r][t];
+    // the same batches out: all LDS reads of a batch before its stores
+    constexpr int PER = SG::rows * NB / PTH, BMAX = PTH >= 1024 ? 8 : 16, BAT = PER < BMAX ? PER : BMAX;
+#pragma unroll
+    for (int q0 = 0; q0 < PER; q0 += BAT) {
+      C64 v[BAT];
+#pragma unroll
+      for (int q = 0; q < BAT; ++q) {
+        const int e = tid + (q0 + q) * PTH;
+        v[q] = s_panel[e / NB][e % NB];
+      }
+#pragma unroll
+      for (int q = 0; q < BAT; ++q) {
+        const int e = tid + (q0 + q) * PTH, r = e / NB, t = e % NB;
+        if (r < n && t < nbe) Anew[(size_t)r * ld + c0 + t] = v[q];
+      }
     }
   } else {
 #pragma unroll
