@@ -136,6 +136,46 @@ def test_config2_accuracy_grid():
 
 
 @pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_degenerate_sizes_against_oracle(mu):
+    """The smallest outer and inner sizes through the whole path on a 2^4
+    lattice, against the oracle at the same (k, l): k = 1 (the result is
+    sgn(Re alpha_0) x), k = 2 with l = 1 and l = 2, and l = k = 40 (the nested
+    form with the inner space as large as the outer one equals the plain form,
+    Sec. 3); and the nested l = k result against the plain one to 1e-10."""
+    dims = (2, 2, 2, 2)
+    lat, u = make_lattice(dims, 0.6, seed=3)
+    x = latgen.random_sources(dims, 1, 3)[0]
+    f = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, mu).reshape(-1)
+    fd = lambda v: W.a_apply(u, v.reshape(x.shape), M_W, -mu).reshape(-1)
+    herm = mu == 0.0
+    for k, ell in ((1, 0), (1, 1), (2, 1), (2, 2), (40, 0), (40, 40)):
+        banner(f"degenerate sizes 2^4 mu={mu} k={k} ell={ell}")
+        y, info, rc = _sign(lat, x, k=k, ell=ell, mu=mu)
+        yo, _ = N.sign_apply(f, fd, x, k, ell, herm)
+        sens = rel(N.sign_apply(f, fd, perturbed(x), k, ell, herm)[0], yo)
+        print(f"[gap] k={k} ell={ell}: GPU vs oracle {rel(y, yo):.3e}, sensitivity {sens:.3e}", flush=True)
+        assert rc in (0, b_warn()) and info.k_used == k
+        assert rel(y, yo) <= method_bound(sens)
+        if k == 1:
+            assert rel(y, np.sign(info_alpha0(lat, x, mu)) * x.reshape(-1)) < 1e-12
+    yp, _, _ = _sign(lat, x, k=40, ell=0, mu=mu)
+    yn, _, _ = _sign(lat, x, k=40, ell=40, mu=mu)
+    assert rel(yn, yp) < 1e-10
+    lat.close()
+
+
+def b_warn():
+    return nk().NK_WARN_NOTCONV
+
+
+def info_alpha0(lat, x, mu):
+    """Re alpha_0 = Re x^dag A x / |x|^2 from the library's basis call."""
+    b = nk()
+    al, be, de, info, _ = b.nk_krylov_basis_device(lat.h, b.nk_sign_params_default(k=1, mu=mu, m_w=M_W), to_dev(x))
+    return al[0].real
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
 def test_full_size_free_field_exact(mu):
     dims = (16, 16, 16, 16)
     banner(f"free field 16^4 exact level mu={mu}")
