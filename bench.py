@@ -387,7 +387,9 @@ def main() -> int:
     eps_plain = rel(y, yref)
 
     def timed(nsteps, **kw):
-        """Wall time per application over nsteps after one warm-up; summed info fields."""
+        """Wall time per application over nsteps after one warm-up, with the same
+        kernel-event sampling as the headline's timed steps; summed info fields."""
+        kw.setdefault("profile", PROFILE_EVERY)
         nk.nk_sign_apply_device(lat.h, params(**kw), x, y)
         torch.cuda.synchronize()
         acc = {"t_stencil_ms": 0.0, "n_stencil": 0, "t_update_ms": 0.0, "n_update": 0, "t_basis_ms": 0.0,
@@ -422,11 +424,34 @@ def main() -> int:
     t_nested = (time.perf_counter() - t0) / args.steps
     t_st, n_st, t_up, n_up = st["t_stencil_ms"], st["n_stencil"], st["t_update_ms"], st["n_update"]
 
-    # the other forms at the same k, fewer steps (timed for the comparison only)
+    # the other forms at the same k, as many steps and the same event sampling
+    # as the headline (timed for the comparison only)
     nside = max(1, args.steps // 2)
-    t_plain, info_p = timed(nside, k=args.k, ell=0)
-    t_nested_u, info_u = timed(nside, k=args.k, ell=args.ell)
-    t_nested_d, info_d = timed(nside, k=args.k, ell=args.ell, scaling=nk.NK_RH_DET)
+    t_plain, info_p = timed(args.steps, k=args.k, ell=0)
+    t_nested_u, info_u = timed(args.steps, k=args.k, ell=args.ell)
+    t_nested_d, info_d = timed(args.steps, k=args.k, ell=args.ell, scaling=nk.NK_RH_DET)
+    # the three nested scalings and the plain form interleaved, one application of
+    # each per round with the order rotated every round (so that no form always
+    # follows the same one), so that clock drift between timing blocks cancels:
+    # median wall time of each form's applications (each bracketed by
+    # synchronisation)
+    inter_forms = {"nested_learned": dict(scaling=LEARNED), "nested_determinant": dict(scaling=nk.NK_RH_DET),
+                   "nested_unscaled": dict(scaling=nk.NK_RH_NONE), "plain_unscaled": dict(ell=0)}
+    inter_t = {f: [] for f in inter_forms}
+    names = list(inter_forms)
+    nrounds = 4 * max(2, (args.steps + 3) // 4)
+    for rr in range(nrounds):
+        for f in names[rr % 4:] + names[:rr % 4]:
+            kw = inter_forms[f]
+            kw2 = dict(k=args.k, ell=args.ell, profile=PROFILE_EVERY)
+            kw2.update(kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nk.nk_sign_apply_device(lat.h, params(**kw2), x, y)
+            torch.cuda.synchronize()
+            inter_t[f].append(time.perf_counter() - t0)
+    forms_interleaved = {f: {"applies_per_s": 1.0 / float(np.median(v)), "ms_median": float(np.median(v)) * 1e3,
+                             "ms_min": min(v) * 1e3, "rounds": len(v)} for f, v in inter_t.items()}
     # many sources in lockstep (nested, learned scaling): per-source rate
     nb = args.batch
     xb = torch.from_numpy(latgen.random_sources(DIMS, nb, 1).reshape(-1)).to(dev)
@@ -770,14 +795,15 @@ def main() -> int:
             "nested_learned": {"applies_per_s": 1.0 / t_nested, "rh_iters": rh_iters,
                                "small_ms": ph["small"] / args.steps},
             "nested_determinant": {"applies_per_s": 1.0 / t_nested_d, "rh_iters": info_d["rh_iters"],
-                                   "small_ms": info_d["t_small_ms"] / nside},
+                                   "small_ms": info_d["t_small_ms"] / args.steps},
             "nested_unscaled": {"applies_per_s": 1.0 / t_nested_u, "rh_iters": info_u["rh_iters"],
-                                "small_ms": info_u["t_small_ms"] / nside},
+                                "small_ms": info_u["t_small_ms"] / args.steps},
             "plain_unscaled": {"applies_per_s": 1.0 / t_plain, "rh_iters": info_p["rh_iters"],
-                               "small_ms": info_p["t_small_ms"] / nside},
+                               "small_ms": info_p["t_small_ms"] / args.steps},
             f"nested_learned_batched_{nb}": {"applies_per_s_per_source": nb / t_batch, "ms_per_batch": t_batch * 1e3,
                                              "two_pass": info_b.two_pass},
         },
+        "forms_interleaved": forms_interleaved,
         "nested_vs_plain_speedup": t_plain / t_nested,
         "rh_inverse_shape_k": nk.nk_rh_tile_choice(args.k, 1),
         "learned_model": os.path.relpath(rh_train.WEIGHTS, ROOT) if have_model else None,

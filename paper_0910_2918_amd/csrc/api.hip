@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "hostbuf.h"
 #include "nk_internal.h"
 
 namespace nk {
@@ -48,6 +49,28 @@ int DevBuf::ensure(size_t need) {
 void DevBuf::release() {
   if (p) (void)hipFree(p);
   p = nullptr;
+  bytes = 0;
+}
+
+int HostBuf::ensure(size_t need) {
+  if (h && need <= bytes) return NK_OK;
+  release();
+  if (need == 0) return NK_OK;
+  hipError_t e = hipHostMalloc(&h, need, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(&d, h, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    set_error("pinned host allocation of %zu bytes failed: %s", need, hipGetErrorString(e));
+    return NK_ENOMEM;
+  }
+  bytes = need;
+  return NK_OK;
+}
+
+void HostBuf::release() {
+  if (h) (void)hipHostFree(h);
+  h = d = nullptr;
   bytes = 0;
 }
 
@@ -109,6 +132,19 @@ static int validate_params(nk_lattice* lat, const nk_sign_params* p) {
     set_error("check_every must be >= 1 when tol > 0");
     return NK_EINVAL;
   }
+  return NK_OK;
+}
+
+// the outer recurrence's status flag, read through pinned memory (one DMA
+// and a synchronisation, no staging through pageable memory)
+namespace {
+HostBuf g_flag_pin;
+}
+static int read_flag(const int* dflag, hipStream_t st, int* out) {
+  if (g_flag_pin.ensure(sizeof(int))) return NK_ENOMEM;
+  NK_HIP(hipMemcpyAsync(g_flag_pin.h, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipStreamSynchronize(st));
+  *out = *g_flag_pin.host<int>();
   return NK_OK;
 }
 
@@ -199,8 +235,7 @@ static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64
     if (int e = basis_run(lat, bp, cb.xd, j0, j1, cb.c, lat->vk.p, st, nullptr)) return e;
     j0 = j1;
     if (p->tol > 0.0 && j1 < k) {
-      NK_HIP(hipMemcpyAsync(&flag, cb.c.flags, sizeof(int), hipMemcpyDeviceToHost, st));
-      NK_HIP(hipStreamSynchronize(st));
+      if (int e = read_flag(cb.c.flags, st, &flag)) return e;
       if (flag) break;
       const int d = std::max(1, std::min(p->est_delay > 0 ? p->est_delay : 10, j1 - 1));
       if (j1 - d < 1) continue;
@@ -214,8 +249,7 @@ static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64
     }
   }
   NK_HIP(hipEventRecord(ev[1], st));
-  NK_HIP(hipMemcpyAsync(&flag, cb.c.flags, sizeof(int), hipMemcpyDeviceToHost, st));
-  NK_HIP(hipStreamSynchronize(st));
+  if (int e = read_flag(cb.c.flags, st, &flag)) return e;
   int warn = NK_OK;
   if (flag < 0) {
     set_error("source vector has zero or non-finite norm");

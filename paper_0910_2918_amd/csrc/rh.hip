@@ -36,10 +36,13 @@
 // unchanged) and emits partial sums of |S_{n+1} - S_n|_F^2 and
 // |S_{n+1}|_F^2 for the host's stopping test.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <map>
 #include <mutex>
 
+#include "hostbuf.h"
 #include "nk_internal.h"
 
 namespace nk {
@@ -102,10 +105,18 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
   C64* Anew = Anew_b + off;
   int* rowof = rowof_b + (size_t)b * ld;
   int* posof = posof_b + (size_t)b * ld;
-  __shared__ unsigned s_key[2][NW];
-  __shared__ C64 s_prow[2][NB];
-  __shared__ int s_piv[NB];  // pivot rows of the panel, written to memory after the last column
-  __shared__ C64 s_panel[SG::rows][NB + 1];
+  // one LDS block with the small arrays first, so that their addresses fit the
+  // immediate offset of an LDS instruction
+  __shared__ struct {
+    C64 prow[2][NB];
+    unsigned key[2][NW];
+    int piv[NB];  // pivot rows of the panel, written to memory after the last column
+    C64 panel[SG::rows][NB + 1];
+  } sh;
+  auto& s_key = sh.key;
+  auto& s_prow = sh.prow;
+  auto& s_piv = sh.piv;
+  auto& s_panel = sh.panel;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   C64 a[RM][NB];
   bool used[RM];
@@ -172,12 +183,17 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
       // while t < n - c0 an unused row remains, so best != 0; a zero key
       // would only leave pr = -1 (no row replaced) and a zero multiplier
       const int pr = best ? 8191 - (int)(best & 0x1FFFu) : -1;
-      // 2. the pivot row's owner hands its row to every thread
+      // 2. the pivot row's owner hands its row to every thread, then sets its
+      //    own copy to -e_t, so that the common update of step 3 turns it into
+      //    the scaled pivot row
 #pragma unroll
       for (int m = 0; m < RM; ++m)
-        if (tid + m * PTH == pr)
+        if (tid + m * PTH == pr) {
 #pragma unroll
           for (int u = 0; u < NB; ++u) s_prow[par][u] = a[m][u];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) a[m][u] = mk(u == t ? -1.0 : 0.0, 0.0);
+        }
       if (tid == 0) s_piv[t] = pr;
       __syncthreads();
       // the pivot row in registers, all of it read before any use (one LDS
@@ -206,25 +222,24 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
         dm = frexp(dm * norm2(piv), &ex);
         de += ex;
       }
-      // 3. one branch-free update for every row: a[u] = keep * a[u] - g * p[u]
-      // with p the pivot row (p[t] replaced by 1) and
-      //   other rows: keep = 1 (0 in column t), g = a[t] / piv, so column t
-      //               becomes -a[t] / piv;
-      //   pivot row:  keep = 0, g = -1 / piv, so the row becomes p / piv
-      //               with 1 / piv in column t
+      // 3. one branch-free update for every row, with p the pivot row and
+      //    g = a[t] / piv:  a[t] = -g,  a[u] = a[u] - g p[u] (u != t).
+      //    Other rows: column t becomes -a[t] / piv.  The pivot row holds -e_t
+      //    (step 2), so g = -1 / piv and the row becomes p / piv with 1 / piv
+      //    in column t.
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const bool isp = tid + m * PTH == pr;
-        const C64 fd = cmul(a[m][t], d);
-        const C64 g = isp ? mk(-d.re, -d.im) : fd;
-        const double keep = isp ? 0.0 : 1.0;
+        const C64 g = cmul(a[m][t], d);
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-          const C64 p = (u == t) ? mk(1.0, 0.0) : prow_at(u);
-          const double kr = (u == t) ? 0.0 : keep * a[m][u].re, ki = (u == t) ? 0.0 : keep * a[m][u].im;
-          a[m][u] = mk(fma(g.im, p.im, fma(-g.re, p.re, kr)), fma(-g.im, p.re, fma(-g.re, p.im, ki)));
+          if (u == t) {
+            a[m][u] = mk(-g.re, -g.im);
+          } else {
+            const C64 p = prow_at(u);
+            a[m][u] = mk(fma(g.im, p.im, fma(-g.re, p.re, a[m][u].re)), fma(-g.im, p.re, fma(-g.re, p.im, a[m][u].im)));
+          }
         }
-        if (isp) used[m] = true;
+        if (tid + m * PTH == pr) used[m] = true;
       }
     }
   }
@@ -360,6 +375,40 @@ __global__ void k_gjstart(int ld, int batch, const int* __restrict__ nvec, const
   if (blockIdx.x == 0 && threadIdx.x == 0) logdet[b] = 0.0;
 }
 
+// The host's stopping sums of every matrix (one workgroup each): the
+// inversion step's |S_{n+1} - S_n|^2 and |S_{n+1}|^2 partials (k_gjcombine,
+// nbl pairs) and the Newton-Schulz kernels' pairs (k_ns_gemm, ntile2 pairs),
+// each thread adding a strided subset, then a fixed-order tree, so the sums do
+// not depend on timing.  They go straight into host memory (out, four per
+// matrix), where the host has left a sentinel bit pattern that it polls for
+// being overwritten; partials a step did not write are summed too and
+// ignored by the host.
+__global__ void __launch_bounds__(256) k_rh_sums(int nbl, const double* __restrict__ part, int ntile2,
+                                                 const double* __restrict__ nspart, double* __restrict__ out) {
+  const int b = blockIdx.x;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nbl; i += 256) {
+    v[0] += part[((size_t)b * nbl + i) * 2 + 0];
+    v[1] += part[((size_t)b * nbl + i) * 2 + 1];
+  }
+  for (int i = threadIdx.x; i < ntile2; i += 256) {
+    v[2] += nspart[((size_t)b * ntile2 + i) * 2 + 0];
+    v[3] += nspart[((size_t)b * ntile2 + i) * 2 + 1];
+  }
+  __shared__ double sh[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh[q][threadIdx.x >> 6] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[b * 4 + q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+}
+
 // G0/G1: the ping-pong buffers; a matrix of order n ends its elimination in
 // the buffer of its own last panel, (ceil(n / nb) - 1) % 2.
 // S_{n+1}[posof[r]][rowof[c]] = (mu S_n[..][..] + X[r][c] / mu) / 2
@@ -368,14 +417,18 @@ __global__ void __launch_bounds__(256) k_gjcombine(int ld, int nb, const int* __
                                                    const C64* __restrict__ G1, C64* __restrict__ X_b,
                                                    const int* __restrict__ rowof_b, const int* __restrict__ posof_b,
                                                    const double* __restrict__ logdet, int scaling,
-                                                   const double* __restrict__ mu_in, double* __restrict__ part) {
+                                                   const double* __restrict__ mu_sched, int mu_steps, int step,
+                                                   double* __restrict__ part) {
   const int b = blockIdx.y;
   const int n = nvec[b];
   double dsum = 0.0, nsum = 0.0;
   if (active[b]) {
     double mu = 1.0;
     if (scaling == NK_RH_DET || scaling == NK_RH_LEARNED) mu = exp(-logdet[b] / n);
-    if (scaling == NK_RH_LEARNED && mu_in && mu_in[b] > 0.0) mu *= mu_in[b];  // learned correction
+    if (scaling == NK_RH_LEARNED && mu_sched && step < mu_steps) {  // learned correction of this step
+      const double m = mu_sched[(size_t)b * mu_steps + step];
+      if (m > 0.0) mu *= m;
+    }
     const double imu = 1.0 / mu;
     const size_t off = (size_t)b * ld * ld;
     const int npan = (n + nb - 1) / nb;
@@ -744,7 +797,9 @@ __global__ void __launch_bounds__(ST_RH) k_rh_small(int ld, const int* __restric
 // ---------------------------------------------------------------------------
 namespace {
 std::mutex g_rh_mu;
-DevBuf g_G0, g_G1, g_int, g_dbl, g_mu, g_sched, g_nsp;
+DevBuf g_G0, g_G1, g_int, g_dbl, g_sched, g_nsp;
+// pinned staging of the large path: flag uploads and the stopping sums
+HostBuf g_pin, g_pinr;
 // the Newton-Schulz tail of the large path (nk_rh_newton_schulz); on by default
 int g_ns_tail = 1;
 }  // namespace
@@ -917,22 +972,25 @@ int rh_tile_choice(int maxn, int batch, int* nb, int* rm, int* pth, int* tile) {
 
 // |S^2 - I|_F / sqrt(n) of every matrix of the batch into resid_host: one
 // product S S on the matrix cores (k_ns_gemm<0>, which leaves 3 I - S^2 in the
-// scratch buffer G0 and the partial sums of |I - S^2|_F^2), then the sums
-static int rh_residuals(int batch, int ld, int maxn, const int* nvec, const C64* S, double* resid,
-                        double* resid_host, hipStream_t st) {
+// scratch buffer G0 and the partial sums of |I - S^2|_F^2), then the sums,
+// written by k_rh_resid_sum straight into pinned host memory
+static int rh_residuals(int batch, int maxn, int ld, const int* nvec, const C64* S, double* resid_host,
+                        hipStream_t st) {
   const int ntile = (maxn + 31) / 32;
   const size_t nsp = (size_t)batch * ntile * ntile * 2;
   if (g_nsp.ensure(nsp * sizeof(double) + (size_t)batch * sizeof(int))) return NK_ENOMEM;
+  if (g_pinr.ensure((size_t)batch * (sizeof(double) + sizeof(int)))) return NK_ENOMEM;
   double* part = g_nsp.as<double>();
   int* all = reinterpret_cast<int*>(part + nsp);
-  std::vector<int> ones(batch, 1);
-  NK_HIP(hipMemcpyAsync(all, ones.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+  int* ones = reinterpret_cast<int*>(g_pinr.host<double>() + batch);
+  std::fill(ones, ones + batch, 1);
+  NK_HIP(hipMemcpyAsync(all, ones, batch * sizeof(int), hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_ns_gemm<0>, dim3(ntile, ntile, batch), dim3(256), 0, st, ld, nvec, all, S, S, g_G0.as<C64>(),
                      part);
-  hipLaunchKernelGGL(k_rh_resid_sum, dim3(batch), dim3(256), 0, st, ntile * ntile, nvec, part, resid);
+  hipLaunchKernelGGL(k_rh_resid_sum, dim3(batch), dim3(256), 0, st, ntile * ntile, nvec, part, g_pinr.dev<double>());
   NK_HIP(hipGetLastError());
-  NK_HIP(hipMemcpyAsync(resid_host, resid, batch * sizeof(double), hipMemcpyDeviceToHost, st));
-  NK_HIP(hipStreamSynchronize(st));  // ones stays alive until its copy has been consumed
+  NK_HIP(hipStreamSynchronize(st));
+  std::copy(g_pinr.host<double>(), g_pinr.host<double>() + batch, resid_host);
   return NK_OK;
 }
 
@@ -947,7 +1005,7 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   const size_t mb = (size_t)batch * ld * ld * sizeof(C64);
   const int nbl = 64;
   if (g_G0.ensure(mb) || g_G1.ensure(mb) || g_int.ensure((size_t)batch * (2 * ld + 4) * sizeof(int)) ||
-      g_dbl.ensure((size_t)batch * (2 * nbl + 4) * sizeof(double)) || g_mu.ensure((size_t)batch * sizeof(double)))
+      g_dbl.ensure((size_t)batch * (2 * nbl + 4) * sizeof(double)))
     return NK_ENOMEM;
   int* nvec = g_int.as<int>();
   int* act = nvec + batch;
@@ -957,12 +1015,35 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
   double* logdet = g_dbl.as<double>();
   double* resid = logdet + batch;
   double* part = resid + batch;
-  double* mu_dev = g_mu.as<double>();
+
+  // Pinned, device-mapped staging (the previous call ended with a stream
+  // synchronisation, so none of it is still in use): seven int arrays (the
+  // orders, zeros, the initial active set, the inversion and Newton-Schulz
+  // flags of the large path, the returned iteration counts and states) and
+  // four stopping sums per matrix, which k_rh_sums writes into host memory.
+  // Each flag array is uploaded only when its content changes and rewritten
+  // only once later work of the stream has been seen to finish (so its last
+  // upload has been consumed), and every host decision waits for one small
+  // kernel's results instead of copies through pageable memory and a stream
+  // synchronisation.
+  const size_t pin_ints = (7 * (size_t)batch + 1) & ~(size_t)1;  // keeps the sums 8-byte aligned
+  if (g_pin.ensure(pin_ints * sizeof(int) + 4 * (size_t)batch * sizeof(double))) return NK_ENOMEM;
+  int* pin_n = g_pin.host<int>();
+  int* pin_zero = pin_n + batch;
+  int* pin_act0 = pin_zero + batch;
+  int* pin_gj = pin_act0 + batch;
+  int* pin_ns = pin_gj + batch;
+  int* pin_iters = pin_ns + batch;
+  int* pin_state = pin_iters + batch;
+  const double* sums_h = reinterpret_cast<const double*>(g_pin.host<int>() + pin_ints);
+  double* sums_d = reinterpret_cast<double*>(g_pin.dev<int>() + pin_ints);
 
   int maxn = 0;
-  std::vector<int> act_h(batch), zeros(batch, 0);
+  std::vector<int> act_h(batch);
   for (int b = 0; b < batch; ++b) maxn = std::max(maxn, n_host[b]);
-  NK_HIP(hipMemcpyAsync(nvec, n_host, batch * sizeof(int), hipMemcpyHostToDevice, st));
+  std::copy(n_host, n_host + batch, pin_n);
+  std::fill(pin_zero, pin_zero + batch, 0);
+  NK_HIP(hipMemcpyAsync(nvec, pin_n, batch * sizeof(int), hipMemcpyHostToDevice, st));
   // learned scaling: the installed model's factors for the first steps of
   // each matrix, predicted from S_0 (without a model: determinant scaling)
   const int mu_steps = NK_MLP_STEPS;
@@ -974,7 +1055,7 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     if (have) mdev = g_sched.as<double>();
   }
   if (maxn <= SMAX) {
-    NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+    NK_HIP(hipMemcpyAsync(sing, pin_zero, batch * sizeof(int), hipMemcpyHostToDevice, st));
     int rps = 0;  // largest rows-per-thread over the batch
     for (int b = 0; b < batch; ++b)
       if (n_host[b] > 0) rps = std::max(rps, (n_host[b] + ST_RH / n_host[b] - 1) / (ST_RH / n_host[b]));
@@ -997,13 +1078,13 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
       hipLaunchKernelGGL(k_rh_small<32>, dim3(batch), dim3(ST_RH), 0, st, ld, nvec, S, scaling, mdev, mu_steps, maxit,
                          tol, act, sing);
     NK_HIP(hipGetLastError());
-    std::vector<int> sing_h(batch);
-    NK_HIP(hipMemcpyAsync(iters_host, act, batch * sizeof(int), hipMemcpyDeviceToHost, st));
-    NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(pin_iters, act, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+    NK_HIP(hipMemcpyAsync(pin_state, sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
     if (resid_host)
-      if (int e = rh_residuals(batch, ld, maxn, nvec, S, resid, resid_host, st)) return e;
+      if (int e = rh_residuals(batch, maxn, ld, nvec, S, resid_host, st)) return e;
     NK_HIP(hipStreamSynchronize(st));
-    return rh_outcome(batch, sing_h.data(), maxit);
+    std::copy(pin_iters, pin_iters + batch, iters_host);
+    return rh_outcome(batch, pin_state, maxit);
   }
   maxn = 0;
   for (int b = 0; b < batch; ++b) {
@@ -1011,29 +1092,65 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     act_h[b] = n_host[b] > 0 ? 1 : 0;
     iters_host[b] = 0;
   }
-  NK_HIP(hipMemcpyAsync(act, act_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+  std::copy(act_h.begin(), act_h.end(), pin_act0);
+  NK_HIP(hipMemcpyAsync(act, pin_act0, batch * sizeof(int), hipMemcpyHostToDevice, st));
   // Newton-Schulz tail: workspace and per-matrix state (0: inversion steps,
-  // 1: Newton-Schulz steps, entered once |I - S^2|_F < 1/2)
+  // 1: Newton-Schulz steps, entered once |I - S^2|_F < 1/2 and kept)
   const int ntile = (maxn + 31) / 32;
-  const size_t nsp = (size_t)batch * ntile * ntile * 2;
+  const int ntile2 = ntile * ntile;
+  const size_t nsp = (size_t)batch * ntile2 * 2;
   if (g_nsp.ensure(nsp * sizeof(double) + (size_t)batch * sizeof(int))) return NK_ENOMEM;
   double* nspart = g_nsp.as<double>();
   int* act_ns = reinterpret_cast<int*>(nspart + nsp);
   std::vector<int> ns_h(batch, 0), try_h(batch, 0), gj_h(batch, 0);
-  std::vector<double> nsp_h(nsp);
+  // the device content of act and act_ns as last uploaded (-1: unknown)
+  std::vector<int> dev_act(act_h), dev_ns(batch, -1);
   const int ns_on = g_ns_tail;
   GJShape shape;
   if (int e = gj_choose(batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), rowof, posof, logdet, sing, st,
                         &shape))
     return e;
-  NK_HIP(hipMemcpyAsync(sing, zeros.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
-  std::vector<double> prev(batch, INFINITY), part_h((size_t)batch * nbl * 2), mu_h(batch, 1.0);
-  std::vector<double> sched_h;
-  if (mdev) {
-    sched_h.resize((size_t)batch * mu_steps);
-    NK_HIP(hipMemcpyAsync(sched_h.data(), mdev, sched_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    NK_HIP(hipStreamSynchronize(st));
-  }
+  NK_HIP(hipMemcpyAsync(sing, pin_zero, batch * sizeof(int), hipMemcpyHostToDevice, st));
+  std::vector<double> prev(batch, INFINITY);
+  // a flag array to the device, only when it differs from its last upload;
+  // the staging slot is rewritten only here, after the stopping sums of a
+  // later point of the stream (or a synchronisation) have been seen, so its
+  // previous upload has been consumed
+  auto upload = [&](int* dev, int* pin, const std::vector<int>& v, std::vector<int>& last) -> int {
+    if (v == last) return NK_OK;
+    std::copy(v.begin(), v.end(), pin);
+    NK_HIP(hipMemcpyAsync(dev, pin, batch * sizeof(int), hipMemcpyHostToDevice, st));
+    last = v;
+    return NK_OK;
+  };
+  // the stopping sums of this point of the stream, in host memory: the host
+  // fills them with a sentinel bit pattern (a NaN no arithmetic produces),
+  // launches k_rh_sums and polls for up to 2 ms until every value is
+  // overwritten (an iteration's kernels are usually done by then); otherwise
+  // it waits on the stream, which also reports any error of the queued work.
+  // Every value is one aligned 8-byte store.  Before each fill the previous
+  // sums have all arrived, so no earlier write can land on a sentinel.
+  constexpr uint64_t kSentinel = 0x7FF4D15EA5E0F00Dull;
+  volatile uint64_t* sums_bits = reinterpret_cast<volatile uint64_t*>(const_cast<double*>(sums_h));
+  auto sums = [&]() -> int {
+    for (int i = 0; i < 4 * batch; ++i) sums_bits[i] = kSentinel;
+    hipLaunchKernelGGL(k_rh_sums, dim3(batch), dim3(256), 0, st, nbl, (const double*)part, ntile2,
+                       (const double*)nspart, sums_d);
+    NK_HIP(hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < 4 * batch;) {
+      if (sums_bits[i] != kSentinel) {
+        ++i;
+        continue;
+      }
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+        NK_HIP(hipStreamSynchronize(st));
+        break;
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return NK_OK;
+  };
   // the step at which a matrix may try the Newton-Schulz test: once its
   // relative change has fallen below this (earlier tests would only fail)
   const double ns_try = 0.05;
@@ -1049,17 +1166,18 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
       anytry = anytry || try_h[b];
     }
     if (anytry) {
-      NK_HIP(hipMemcpyAsync(act_ns, try_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+      if (int e = upload(act_ns, pin_ns, try_h, dev_ns)) return e;
       hipLaunchKernelGGL(k_ns_gemm<0>, dim3(ntile, ntile, batch), dim3(256), 0, st, ld, nvec, act_ns, S, S,
                          g_G0.as<C64>(), nspart);
       NK_HIP(hipGetLastError());
-      NK_HIP(hipMemcpyAsync(nsp_h.data(), nspart, nsp * sizeof(double), hipMemcpyDeviceToHost, st));
-      NK_HIP(hipStreamSynchronize(st));
-      for (int b = 0; b < batch; ++b) {
-        if (!try_h[b]) continue;
-        double r2 = 0.0;
-        for (size_t i = 0; i < (size_t)ntile * ntile; ++i) r2 += nsp_h[((size_t)b * ntile * ntile + i) * 2];
-        ns_h[b] = std::sqrt(r2) < 0.5 ? 1 : 0;
+      // only a matrix not yet in the tail waits for its test: inside it
+      // |I - S^2|_F only falls (see above), so the product is all it needs
+      bool wait = false;
+      for (int b = 0; b < batch; ++b) wait = wait || (try_h[b] && !ns_h[b]);
+      if (wait) {
+        if (int e = sums()) return e;
+        for (int b = 0; b < batch; ++b)
+          if (try_h[b] && !ns_h[b]) ns_h[b] = std::sqrt(sums_h[b * 4 + 2]) < 0.5 ? 1 : 0;
       }
     }
     bool anyns = false, anygj = false;
@@ -1072,59 +1190,42 @@ int rh_sign_batched(int batch, int ld, const int* n_host, C64* S, int scaling, i
     }
     // 2. Newton-Schulz step: G1 = S (3 I - S^2) / 2, then S <- G1
     if (anyns) {
-      NK_HIP(hipMemcpyAsync(act_ns, try_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
+      if (int e = upload(act_ns, pin_ns, try_h, dev_ns)) return e;
       hipLaunchKernelGGL(k_ns_gemm<1>, dim3(ntile, ntile, batch), dim3(256), 0, st, ld, nvec, act_ns, S,
                          g_G0.as<C64>(), g_G1.as<C64>(), nspart);
       hipLaunchKernelGGL(k_ns_copy, dim3(64, batch), dim3(256), 0, st, ld, nvec, act_ns, g_G1.as<C64>(), S);
       NK_HIP(hipGetLastError());
     }
-    // 3. inversion step: S <- (mu S + (mu S)^{-1}) / 2
+    // 3. inversion step: S <- (mu S + (mu S)^{-1}) / 2 (the learned factor of
+    //    step it - 1 read from the device schedule)
     if (anygj) {
-      NK_HIP(hipMemcpyAsync(act, gj_h.data(), batch * sizeof(int), hipMemcpyHostToDevice, st));
-      if (scaling == NK_RH_LEARNED) {
-        for (int b = 0; b < batch; ++b)
-          mu_h[b] = (mdev && it - 1 < mu_steps) ? sched_h[(size_t)b * mu_steps + (it - 1)] : -1.0;
-        NK_HIP(hipMemcpyAsync(mu_dev, mu_h.data(), batch * sizeof(double), hipMemcpyHostToDevice, st));
-      }
+      if (int e = upload(act, pin_gj, gj_h, dev_act)) return e;
       const int nbw = gj_nb(ld);
       launch_inverse_shape(shape, batch, ld, maxn, nvec, act, S, g_G0.as<C64>(), g_G1.as<C64>(), rowof, posof, logdet,
                            sing, st);
       const int rs = scaling == NK_RH_LEARNED ? NK_RH_LEARNED : (scaling == NK_RH_DET ? NK_RH_DET : NK_RH_NONE);
       hipLaunchKernelGGL(k_gjcombine, dim3(nbl, batch), dim3(256), 0, st, ld, nbw, nvec, act, g_G0.as<C64>(),
-                         g_G1.as<C64>(), S, rowof, posof, logdet, rs, mu_dev, part);
+                         g_G1.as<C64>(), S, rowof, posof, logdet, rs, mdev, mu_steps, it - 1, part);
       NK_HIP(hipGetLastError());
-      NK_HIP(hipMemcpyAsync(part_h.data(), part, part_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     }
-    if (anyns) NK_HIP(hipMemcpyAsync(nsp_h.data(), nspart, nsp * sizeof(double), hipMemcpyDeviceToHost, st));
-    NK_HIP(hipStreamSynchronize(st));
+    if (int e = sums()) return e;
     for (int b = 0; b < batch; ++b) {
       if (!act_h[b]) continue;
-      double d = 0.0, nn = 0.0;
-      if (ns_h[b]) {
-        for (size_t i = 0; i < (size_t)ntile * ntile; ++i) {
-          d += nsp_h[((size_t)b * ntile * ntile + i) * 2 + 0];
-          nn += nsp_h[((size_t)b * ntile * ntile + i) * 2 + 1];
-        }
-      } else {
-        for (int i = 0; i < nbl; ++i) {
-          d += part_h[((size_t)b * nbl + i) * 2 + 0];
-          nn += part_h[((size_t)b * nbl + i) * 2 + 1];
-        }
-      }
+      const double d = ns_h[b] ? sums_h[b * 4 + 2] : sums_h[b * 4 + 0];
+      const double nn = ns_h[b] ? sums_h[b * 4 + 3] : sums_h[b * 4 + 1];
       const double change = std::sqrt(d / nn);
       iters_host[b] = it;
       if (!(change > tol) || (change < 1e-6 && change > 0.5 * prev[b])) act_h[b] = 0;
       prev[b] = change;
     }
   }
-  std::vector<int> sing_h(batch);
-  NK_HIP(hipMemcpyAsync(sing_h.data(), sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
+  NK_HIP(hipMemcpyAsync(pin_state, sing, batch * sizeof(int), hipMemcpyDeviceToHost, st));
   if (resid_host)
-    if (int e = rh_residuals(batch, ld, maxn, nvec, S, resid, resid_host, st)) return e;
+    if (int e = rh_residuals(batch, maxn, ld, nvec, S, resid_host, st)) return e;
   NK_HIP(hipStreamSynchronize(st));
   for (int b = 0; b < batch; ++b)
-    if (act_h[b] && !sing_h[b]) sing_h[b] = 2;  // still active after maxit iterations
-  return rh_outcome(batch, sing_h.data(), maxit);
+    if (act_h[b] && !pin_state[b]) pin_state[b] = 2;  // still active after maxit iterations
+  return rh_outcome(batch, pin_state, maxit);
 }
 
 }  // namespace nk

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <vector>
 
+#include "hostbuf.h"
 #include "nk_internal.h"
 
 namespace nk {
@@ -709,6 +710,7 @@ __global__ void k_col0(int k, const C64* __restrict__ S, C64* __restrict__ z) {
 // ---------------------------------------------------------------------------
 namespace {
 DevBuf g_small, g_batch;
+HostBuf g_small_pin;  // pinned readback of the inner iteration's flags
 }
 
 // device pointers of the tridiagonal factorisation of H_k
@@ -830,15 +832,13 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
   const size_t lay = inner_layout(k, ell, oneside, nullptr, nullptr, nullptr);
   const size_t oS = (lay + 255) & ~(size_t)255;
   const size_t oD = oS + (((size_t)ell * ell * sizeof(C64) + 255) & ~(size_t)255);
-  if (g_small.ensure(oD + 256)) return NK_ENOMEM;
+  if (g_small.ensure(oD) || g_small_pin.ensure(2 * sizeof(int))) return NK_ENOMEM;
   char* base = g_small.as<char>();
   Inner s;
   TriWork tw;
   inner_layout(k, ell, oneside, base, &s, &tw);
   s.arnoldi = arnoldi;
   C64* Hl = (C64*)(base + oS);
-  Inner* sdev = (Inner*)(base + oD);
-  NK_HIP(hipMemcpyAsync(sdev, &s, sizeof s, hipMemcpyHostToDevice, st));
   if (int e = inner_prepare(k, oneside, alpha, beta, delta, s, tw, st)) return e;
   const int sides = oneside ? 1 : 2;
   for (int i = 0; i < ell; ++i) {
@@ -847,9 +847,8 @@ int small_sign_dev(int k, int ell, int hermitian, const C64* alpha, const C64* b
     if (i + 1 < ell) hipLaunchKernelGGL(k_in_sub<false>, dim3(s.nb2, 1, 1), dim3(ST), 0, st, s, nullptr, i, 1);
   }
   NK_HIP(hipGetLastError());
-  int* iflags = s.flags;
-  int fl[2] = {0, 0};
-  NK_HIP(hipMemcpyAsync(fl, iflags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  int* fl = g_small_pin.host<int>();
+  NK_HIP(hipMemcpyAsync(fl, s.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   NK_HIP(hipStreamSynchronize(st));
   if (fl[1]) {
     set_error("nested small problem: H_k is singular");
