@@ -156,23 +156,28 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
         a[m][t] = (r < n && t < nbe) ? Aold[(size_t)r * ld + c0 + t] : mk(0.0, 0.0);
     }
   }
+  // the wave's largest pivot key of column tc over its unused rows
+  auto col_key = [&](int tc) -> unsigned {
+    unsigned key = 0;
+#pragma unroll
+    for (int m = 0; m < RM; ++m)
+      if (!used[m]) {
+        const unsigned kk = gj_key(cabs1(a[m][tc]), tid + m * PTH);
+        key = kk > key ? kk : key;
+      }
+    return wave_max_u32(key);
+  };
   // |det| of the panel's pivots as a running mantissa and binary exponent
   double dm = 1.0;
   int de = 0, bad = 0;
+  unsigned wkey = col_key(0);  // c0 < n, so the panel has a column 0
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     if (t < nbe) {
       const int par = t & 1;
-      // 1. every wave's largest key, then (after a barrier) the block's
-      unsigned key = 0;
-#pragma unroll
-      for (int m = 0; m < RM; ++m)
-        if (!used[m]) {
-          const unsigned kk = gj_key(cabs1(a[m][t]), tid + m * PTH);
-          key = kk > key ? kk : key;
-        }
-      const unsigned wmax = wave_max_u32(key);
-      if (lane == 0) s_key[par][wid] = wmax;
+      // 1. every wave's largest key (formed during the previous column's
+      //    update), then (after a barrier) the block's
+      if (lane == 0) s_key[par][wid] = wkey;
       __syncthreads();
       unsigned best = 0;
 #pragma unroll
@@ -193,19 +198,22 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
           for (int u = 0; u < NB; ++u) s_prow[par][u] = a[m][u];
 #pragma unroll
           for (int u = 0; u < NB; ++u) a[m][u] = mk(u == t ? -1.0 : 0.0, 0.0);
+          used[m] = true;
         }
       if (tid == 0) s_piv[t] = pr;
       __syncthreads();
       // the pivot row in registers, all of it read before any use (one LDS
       // round trip, not one per entry) where the register budget allows it
-      // (up to 512 threads: two waves per SIMD)
+      // (up to 512 threads: two waves per SIMD); the pivot itself first, so
+      // that its reciprocal is formed while the rest arrives
       constexpr bool REGROW = PTH < 1024;
       C64 prow[REGROW ? NB : 1];
       if constexpr (REGROW) {
+        prow[t] = s_prow[par][t];
 #pragma unroll
-        for (int u = 0; u < NB; ++u) prow[u] = s_prow[par][u];
-#pragma unroll
-        for (int u = 0; u < NB; ++u) asm volatile("" : "+v"(prow[u].re), "+v"(prow[u].im));
+        for (int u = 0; u < NB; ++u)
+          if (u != t) prow[u] = s_prow[par][u];
+        asm volatile("" : "+v"(prow[t].re), "+v"(prow[t].im));
       }
       auto prow_at = [&](int u) -> C64 {
         if constexpr (REGROW)
@@ -222,24 +230,40 @@ __global__ void __launch_bounds__(PTH) k_gjp(int ld, const int* __restrict__ nve
         dm = frexp(dm * norm2(piv), &ex);
         de += ex;
       }
+      if constexpr (REGROW) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+          if (u != t) asm volatile("" : "+v"(prow[u].re), "+v"(prow[u].im));
+      }
       // 3. one branch-free update for every row, with p the pivot row and
       //    g = a[t] / piv:  a[t] = -g,  a[u] = a[u] - g p[u] (u != t).
       //    Other rows: column t becomes -a[t] / piv.  The pivot row holds -e_t
       //    (step 2), so g = -1 / piv and the row becomes p / piv with 1 / piv
-      //    in column t.
+      //    in column t.  Column t + 1 goes first, so that the next column's
+      //    key and its wave maximum overlap the rest of the update.
+      C64 g[RM];
+#pragma unroll
+      for (int m = 0; m < RM; ++m) g[m] = cmul(a[m][t], d);
+      auto upd = [&](int m, int u) {
+        const C64 p = prow_at(u);
+        a[m][u] = mk(fma(g[m].im, p.im, fma(-g[m].re, p.re, a[m][u].re)),
+                     fma(-g[m].im, p.re, fma(-g[m].re, p.im, a[m][u].im)));
+      };
+      if (t + 1 < NB) {
+        const int tn = t + 1 < NB ? t + 1 : t;  // (keeps the index in range where this is dead code)
+#pragma unroll
+        for (int m = 0; m < RM; ++m) upd(m, tn);
+        wkey = col_key(tn);
+      }
 #pragma unroll
       for (int m = 0; m < RM; ++m) {
-        const C64 g = cmul(a[m][t], d);
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-          if (u == t) {
-            a[m][u] = mk(-g.re, -g.im);
-          } else {
-            const C64 p = prow_at(u);
-            a[m][u] = mk(fma(g.im, p.im, fma(-g.re, p.re, a[m][u].re)), fma(-g.im, p.re, fma(-g.re, p.im, a[m][u].im)));
-          }
+          if (u == t)
+            a[m][u] = mk(-g[m].re, -g[m].im);
+          else if (u != t + 1)
+            upd(m, u);
         }
-        if (tid + m * PTH == pr) used[m] = true;
       }
     }
   }
