@@ -431,20 +431,24 @@ def main() -> int:
     t_nested_u, info_u = timed(args.steps, k=args.k, ell=args.ell)
     t_nested_d, info_d = timed(args.steps, k=args.k, ell=args.ell, scaling=nk.NK_RH_DET)
     # the three nested scalings and the plain form interleaved, one application of
-    # each per round with the order rotated every round (so that no form always
-    # follows the same one), so that clock drift between timing blocks cancels:
-    # median wall time of each form's applications (each bracketed by
-    # synchronisation)
+    # each per round with the order rotated every round, so that clock drift
+    # between timing blocks cancels; every timed application follows the same
+    # untimed one (the headline form), so that no form inherits the state
+    # another leaves behind (the plain form's long, latency-bound small problem
+    # would otherwise slow whichever form comes next): median wall time of
+    # each form's applications (each bracketed by synchronisation)
     inter_forms = {"nested_learned": dict(scaling=LEARNED), "nested_determinant": dict(scaling=nk.NK_RH_DET),
                    "nested_unscaled": dict(scaling=nk.NK_RH_NONE), "plain_unscaled": dict(ell=0)}
     inter_t = {f: [] for f in inter_forms}
     names = list(inter_forms)
     nrounds = 4 * max(2, (args.steps + 3) // 4)
+    p_lead = params(args.k, args.ell, profile=PROFILE_EVERY, scaling=LEARNED)
     for rr in range(nrounds):
         for f in names[rr % 4:] + names[:rr % 4]:
             kw = inter_forms[f]
             kw2 = dict(k=args.k, ell=args.ell, profile=PROFILE_EVERY)
             kw2.update(kw)
+            nk.nk_sign_apply_device(lat.h, p_lead, x, y)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             nk.nk_sign_apply_device(lat.h, params(**kw2), x, y)

@@ -70,43 +70,65 @@ __global__ void __launch_bounds__(256) k_rh_features(int ld, const int* __restri
   const int b = blockIdx.x;
   const int n = nvec[b];
   const C64* S = S_b + (size_t)b * ld * ld;
-  // per thread: rows i = tid + 256 m (row sums, Hermitian defect, diagonal)
-  // and columns j = tid + 256 m (column sums)
+  // four consecutive lanes per row i = tid / 4 + 64 m, each adding the
+  // columns j = tid % 4 + 4 q of it (row sums, Hermitian defect), met by
+  // shuffles; the group's first lane keeps the row's statistics (diagonal
+  // entries and the row-sum ones).  The column sums the same way, columns
+  // j = tid / 4 + 64 m over rows i = tid % 4 + 4 q.
+  const int gr = threadIdx.x >> 2, gl = threadIdx.x & 3;
   double fro = 0, rowmax = 0, colmax = 0, herm = 0, dsq = 0, dmax = 0, dmin = INFINITY, rmin = INFINITY;
   double npos = 0, lsum = 0, lsq = 0, radmax = 0, ncross = 0, tr_re = 0, tr_im = 0;
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + gr;
     double rs = 0, rq = 0, hd = 0;
-    for (int j = 0; j < n; ++j) {
-      const C64 a = S[(size_t)i * ld + j];
-      const double m = sqrt(norm2(a));
-      rs += m;
-      rq += m * m;
-      const C64 t = a - conj(S[(size_t)j * ld + i]);
-      hd += norm2(t);
+    if (i < n) {
+#pragma unroll 4
+      for (int j = gl; j < n; j += 4) {
+        const C64 a = S[(size_t)i * ld + j];
+        const double m = sqrt(norm2(a));
+        rs += m;
+        rq += m * m;
+        const C64 t = a - conj(S[(size_t)j * ld + i]);
+        hd += norm2(t);
+      }
     }
-    const C64 d = S[(size_t)i * ld + i];
-    const double ad = sqrt(norm2(d));
-    fro += rq;
-    rowmax = fmax(rowmax, rs);
-    herm += hd;
-    dsq += ad * ad;
-    dmax = fmax(dmax, ad);
-    dmin = fmin(dmin, ad);
-    rmin = fmin(rmin, fabs(d.re));
-    npos += d.re > 0 ? 1.0 : 0.0;
-    const double ld_ = log(ad + TINYF);
-    lsum += ld_;
-    lsq += ld_ * ld_;
-    const double rad = rs - ad;
-    radmax = fmax(radmax, rad);
-    ncross += fabs(d.re) < rad ? 1.0 : 0.0;
-    tr_re += d.re;
-    tr_im += d.im;
+#pragma unroll
+    for (int o = 1; o < 4; o <<= 1) {
+      rs += __shfl_xor(rs, o, 64);
+      rq += __shfl_xor(rq, o, 64);
+      hd += __shfl_xor(hd, o, 64);
+    }
+    if (i < n && gl == 0) {
+      const C64 d = S[(size_t)i * ld + i];
+      const double ad = sqrt(norm2(d));
+      fro += rq;
+      rowmax = fmax(rowmax, rs);
+      herm += hd;
+      dsq += ad * ad;
+      dmax = fmax(dmax, ad);
+      dmin = fmin(dmin, ad);
+      rmin = fmin(rmin, fabs(d.re));
+      npos += d.re > 0 ? 1.0 : 0.0;
+      const double ld_ = log(ad + TINYF);
+      lsum += ld_;
+      lsq += ld_ * ld_;
+      const double rad = rs - ad;
+      radmax = fmax(radmax, rad);
+      ncross += fabs(d.re) < rad ? 1.0 : 0.0;
+      tr_re += d.re;
+      tr_im += d.im;
+    }
   }
-  for (int j = threadIdx.x; j < n; j += 256) {
+  for (int j0 = 0; j0 < n; j0 += 64) {
+    const int j = j0 + gr;
     double cs = 0;
-    for (int i = 0; i < n; ++i) cs += sqrt(norm2(S[(size_t)i * ld + j]));
-    colmax = fmax(colmax, cs);
+    if (j < n) {
+#pragma unroll 4
+      for (int i = gl; i < n; i += 4) cs += sqrt(norm2(S[(size_t)i * ld + j]));
+    }
+#pragma unroll
+    for (int o = 1; o < 4; o <<= 1) cs += __shfl_xor(cs, o, 64);
+    if (j < n && gl == 0) colmax = fmax(colmax, cs);
   }
   __shared__ double sh[4][16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
