@@ -177,6 +177,14 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
   const bool live = s < g.V;
   C64 mine[M];
   hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, xb, w, lane, mine);  // dead lanes hop at site 0
+  __builtin_amdgcn_sched_barrier(0);  // the stencil's registers are free before these loads
+  // this site's input entries go out before the exchange's barrier, which
+  // they then overlap
+  int se = s;
+  asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
+  C64 ein[M];
+#pragma unroll
+  for (int cl = 0; cl < M; ++cl) ein[cl] = in[sidx<double>(g.V, gi * M + cl, live ? se : 0)];
   __syncthreads();
   const size_t kk = (size_t)src * (a.k + 1);
   const double svj = a.sv[kk + j];
@@ -191,14 +199,12 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
   const C64* wj = colw(a, src, j);
   double dre = 0.0, dim = 0.0;
   if (live) {
-    int se = s;
-    asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
 #pragma unroll
     for (int cl = 0; cl < M; ++cl) {
       const int cc = gi * M + cl;
       const C64 hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
       const size_t i = sidx<double>(g.V, cc, se);
-      C64 av = diag * in[i] - 0.5 * hs;
+      C64 av = diag * ein[cl] - 0.5 * hs;
       if (cc >= 6) av = mk(-av.re, -av.im);
       C64 o = cmul(scale, av);
       if (j > 0) o = o - cmul(sub, prev[i]);

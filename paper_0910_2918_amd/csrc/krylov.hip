@@ -285,6 +285,18 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
   Cx<R> mine[M];
   hop_group<NG>(g, live ? s : 0, lk, in, gi, f ? ebt : eft, f ? eft : ebt, xb, w, lane, mine);  // dead lanes hop at site 0
   if (flag) return;
+  __builtin_amdgcn_sched_barrier(0);  // the stencil's registers are free before these loads
+  // this site's input entries go out before the block reduction, whose
+  // barriers they then overlap (the previous vector's as well would take
+  // two registers more than four waves per SIMD allow)
+  int se = s;
+  asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
+  Cx<R> ein[M];
+#pragma unroll
+  for (int cl = 0; cl < M; ++cl) {
+    const size_t i = sidx<R>(g.V, gi * M + cl, live ? se : 0);
+    ein[cl] = in[i];
+  }
   double red[4];
 #pragma unroll
   for (int qd = 0; qd < 4; ++qd) red[qd] = pr[qd];
@@ -323,14 +335,12 @@ __global__ void __launch_bounds__(NT) k_bil1(Geom g, LK lk, R diag, R eft, R ebt
   Cx<R>* out = f ? q : p;
   double dre = 0.0, dim = 0.0;
   if (live) {
-    int se = s;
-    asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
 #pragma unroll
     for (int cl = 0; cl < M; ++cl) {
       const int cc = gi * M + cl;
       const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
       const size_t i = sidx<R>(g.V, cc, se);
-      const Cx<R> ini = in[i];
+      const Cx<R> ini = ein[cl];
       const Cx<R> wpair = pair_swap(ini);  // the odd lane's w_j at this site
       Cx<R> a = diag * ini - R(0.5) * hs;
       if (cc >= 6) a = mk<R>(-a.re, -a.im);
