@@ -26,16 +26,22 @@ __global__ void __launch_bounds__(256) k_apply(Geom g, LK lk, R diag, int g5, Fi
   const bool live = s < g.V;
   Cx<R> mine[M];
   hop_group<NG>(g, live ? s : 0, lk, x, gi, ef, eb, xb, w, lane, mine);  // a lane past the end hops at site 0
-  __syncthreads();
-  if (!live) return;
+  __builtin_amdgcn_sched_barrier(0);  // the stencil's registers are free before these loads
+  // this site's input entries go out before the exchange's barrier, which
+  // they then overlap
   int se = s;
   asm volatile("" : "+v"(se));  // keeps the epilogue addresses out of the stencil's registers
+  Cx<R> ein[M];
+#pragma unroll
+  for (int cl = 0; cl < M; ++cl) ein[cl] = x[sidx<R>(g.V, gi * M + cl, live ? se : 0)];
+  __syncthreads();
+  if (!live) return;
 #pragma unroll
   for (int cl = 0; cl < M; ++cl) {
     const int cc = gi * M + cl;
     const Cx<R> hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
     const size_t i = sidx<R>(g.V, cc, se);
-    Cx<R> o = diag * x[i] - R(0.5) * hs;
+    Cx<R> o = diag * ein[cl] - R(0.5) * hs;
     if (g5 && cc >= 6) o = mk<R>(-o.re, -o.im);
     y[i] = o;
   }
