@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
   C64 ein[M];
 #pragma unroll
   for (int cl = 0; cl < M; ++cl) ein[cl] = in[sidx<double>(g.V, gi * M + cl, live ? se : 0)];
-  __syncthreads();
+  // this source's step coefficients (uniform loads) before the barrier too
   const size_t kk = (size_t)src * (a.k + 1);
   const double svj = a.sv[kk + j];
   const C64 swj = a.sw[kk + j];
@@ -194,9 +194,9 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
     const C64 bm = a.beta[(size_t)src * a.k + j - 1], dm = a.delta[(size_t)src * a.k + j - 1];
     sub = f ? cmul(dm, a.sw[kk + j - 1]) : a.sv[kk + j - 1] * bm;
   }
+  __syncthreads();
   const C64* prev = f ? colw(a, src, j > 0 ? j - 1 : 0) : colv(a, src, j > 0 ? j - 1 : 0);
   C64* out = f ? vq(a, src) : vp(a, src);
-  const C64* wj = colw(a, src, j);
   double dre = 0.0, dim = 0.0;
   if (live) {
 #pragma unroll
@@ -204,13 +204,14 @@ __global__ void __launch_bounds__(BT) k_blk1(Geom g, LinksPlain<double> lk, doub
       const int cc = gi * M + cl;
       const C64 hs = xsum<NG>(xb, sb, gi, lane, cl, mine[cl]);
       const size_t i = sidx<double>(g.V, cc, se);
+      const C64 wpair = pair_swap(ein[cl]);  // the odd lane's w_j at this site
       C64 av = diag * ein[cl] - 0.5 * hs;
       if (cc >= 6) av = mk(-av.re, -av.im);
       C64 o = cmul(scale, av);
       if (j > 0) o = o - cmul(sub, prev[i]);
       out[i] = o;
       if (f == 0) {
-        const C64 t = cmulc(wj[i], av);
+        const C64 t = cmulc(wpair, av);
         dre += t.re;
         dim += t.im;
       }
