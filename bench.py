@@ -823,6 +823,11 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            # the counted traffic per launch over the same launch time, beside
+            # the fastest of this run's own streaming kernels
+            "traffic_GBps": traffic / k1_avg_s / 1e9 if traffic else None,
+            "stream_ceiling_GBps": max((v["GBps"] for v in streams.values() if isinstance(v, dict) and "GBps" in v),
+                                       default=None),
             "avg_launch_us": k1_avg_s * 1e6,
             "launches": int(n_st),
             "bytes_per_launch": k1_bytes,
