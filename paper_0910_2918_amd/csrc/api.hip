@@ -266,7 +266,7 @@ static int sign_one(nk_lattice* lat, const nk_sign_params* p, int ell, const C64
   if (es < 0) return es;
   if (es > 0 && warn == NK_OK) warn = es;
   // the estimate at the final k: requested explicitly (est_delay > 0), or
-  // needed for the early-stop verdict when the loop ran to k without its last
+  // needed for the early-stop decision when the loop ran to k without its last
   // check (the in-loop checks skip j1 == k); the delay is the loop's
   if (std::isnan(est) && (p->est_delay > 0 || p->tol > 0.0)) {
     const int d = std::max(1, std::min(p->est_delay > 0 ? p->est_delay : 10, kused - 1));
