@@ -293,7 +293,8 @@ def main() -> int:
                     help="short run for hardware counters: a copy kernel of known size (1 GiB read, 1 GiB "
                          "written, larger than the 256 MB Infinity Cache) three times, then one application "
                          "at k=20, l=5 of the same workload (same stencil dispatches as the timed run), one "
-                         "deflated application and four sources in lockstep at the same k, l")
+                         "deflated application and four sources in lockstep at the same k, l, then the "
+                         "stand-alone stencil (single operator and fused pair, warm and cold, 20 launches each)")
     ap.add_argument("--calibrate", action="store_true",
                     help="print the relative error of plain and nested runs over a grid of (k, l)")
     args = ap.parse_args()
@@ -360,8 +361,14 @@ def main() -> int:
         nk.nk_sign_apply_device(lat.h, params(20, 5, nrhs=4, block=1), xb4, yb4)
         torch.cuda.synchronize()
         gbs = 2 * n * 16 / (min(times) / 1e3) / 1e9
+        del src, dst, xb4, yb4, rd, ld
+        # the stand-alone stencil, warm and cold, 20 launches each (the only
+        # dispatches of k_apply in the probe, in the order single warm, single
+        # cold, pair warm, pair cold, each after its warm-up launches)
+        st = stencil_rates(torch, nk, latgen, dev, gbs, reps=20)
         print(json.dumps({"probe": "done", "copy_bytes_read": n * 16, "copy_bytes_written": n * 16,
-                          "copy_ms": times, "copy_GBps": gbs}))
+                          "copy_ms": times, "copy_GBps": gbs,
+                          "stencil_us": {k: v["us"] for k, v in st.items() if isinstance(v, dict)}}))
         lat.close()
         return 0
 
